@@ -1,0 +1,204 @@
+/*
+ * tddftb.h - C ABI of the MI355X real-time TD-DFTB propagation library.
+ *
+ * The library propagates the complex one-body density matrix rho of a
+ * density-functional tight-binding model with clamped nuclei under the
+ * Liouville-von Neumann equation in a non-orthogonal basis,
+ *     drho/dt = -i (S^-1 H rho - rho H S^-1)
+ * (Bonafe et al., arXiv 1912.03174, Sec. 2.1, Eq. 10 with the
+ * non-adiabatic coupling D = 0), with the leapfrog integrator and an Euler
+ * start (Sec. 2.3, Eq. 19). At every step the self-consistent-charge
+ * Hamiltonian is rebuilt from the Mulliken charge fluctuations and the
+ * external field (Sec. 2.1, Eqs. 5-7), and the Mulliken dipole is
+ * recorded.
+ *
+ * Conventions shared by every entry point:
+ *  - Atomic units (bohr, hartree, au of time, au of field).
+ *  - Matrices are dense, row-major, float64; complex matrices are
+ *    interleaved complex128 (re, im) pairs, row-major.
+ *  - Orbitals of atom A are contiguous: orbitals orb_offset[A] ..
+ *    orb_offset[A+1]-1.
+ *  - All pointers passed to the library are host pointers unless stated
+ *    otherwise. Input arrays are copied; the caller keeps ownership.
+ *    Output arrays are caller-allocated and written only when the call
+ *    returns TD_OK.
+ *  - Every call returns a td_status. On failure, td_last_error(ctx) holds
+ *    a message (for td_create failures, the message is in the err buffer
+ *    of td_create). No C++ exception crosses the boundary.
+ *  - A context owns one trajectory, its device buffers and one HIP
+ *    stream. Calls on one context must not overlap; different contexts
+ *    are independent.
+ *
+ * Readings of the paper fixed by this interface:
+ *  - Mulliken dipole mu = -sum_A dq_A R_A with dq_A = q_A - q0_A the
+ *    excess electron population (Sec. 2.1, Eq. 5).
+ *  - The external potential entering the Hamiltonian is V_A = R_A . E(t)
+ *    (dipole approximation, Sec. 2.1, relation after Eq. 15).
+ *  - The delta kick multiplies orbital u by exp(-i E0 e . R_A(u))
+ *    (Sec. 2.2, Eq. 16).
+ */
+#ifndef TDDFTB_H
+#define TDDFTB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TD_API __attribute__((visibility("default")))
+
+typedef struct td_ctx td_ctx;
+
+typedef enum {
+  TD_OK = 0,
+  TD_EINVAL = -1,       /* bad argument: null pointer, size, shape, value  */
+  TD_ENOMEM = -2,       /* device or host allocation failed                */
+  TD_EHIP = -3,         /* HIP runtime error (message has the HIP text)    */
+  TD_ENOTPOSDEF = -4,   /* S is not positive definite (inverse diverged)   */
+  TD_ESCF = -5,         /* ground state: SCC or purification not converged */
+  TD_EUNSTABLE = -6,    /* non-finite values after a step                  */
+  TD_ENOTSUP = -7,      /* feature not available in this build             */
+  TD_ESTATE = -8        /* call not valid in the context's current state   */
+} td_status;
+
+typedef enum {
+  TD_FP64 = 0,          /* all products in float64 on the FP64 matrix cores */
+  TD_SPLIT_BF16 = 1     /* products as split-bf16 slices, fp32 accumulation */
+} td_precision;
+
+/* The model: positions, overlap S, non-SCC Hamiltonian H0 (Sec. 2.1,
+ * Eq. 6), charge kernel gamma (Sec. 2.1, Eq. 3), reference populations
+ * q0, and the electron count (closed shell: n_elec / 2 doubly occupied
+ * states). rho0 is optional: NULL asks td_create for the self-consistent
+ * ground state; otherwise it is the initial density matrix,
+ * [n_orb * n_orb] interleaved complex128, Hermitian. */
+typedef struct {
+  int32_t n_atoms;
+  int32_t n_orb;
+  const int32_t *orb_offset;   /* [n_atoms + 1], orb_offset[0] = 0, increasing */
+  const double *positions;     /* [n_atoms * 3] bohr                            */
+  const double *S;             /* [n_orb * n_orb] symmetric positive definite   */
+  const double *H0;            /* [n_orb * n_orb] symmetric, hartree            */
+  const double *gamma;         /* [n_atoms * n_atoms] symmetric, hartree        */
+  const double *q0;            /* [n_atoms] electrons                           */
+  int32_t n_elec;              /* even, 0 < n_elec <= 2 n_orb                   */
+  const double *rho0;          /* optional, see above                           */
+} td_system;
+
+typedef struct {
+  int32_t precision;           /* td_precision                                  */
+  int32_t n_slices;            /* split-bf16 slices per operand (3..6)          */
+  double dt;                   /* time step, au (> 0)                           */
+  double scc_tol;              /* ground state: max |dq_out - dq_in| to stop    */
+  int32_t scc_maxiter;         /* ground state: SCC cycle limit                 */
+  double mix_beta;             /* ground state: Anderson mixing parameter       */
+  int32_t mix_history;         /* ground state: Anderson history (1..8)         */
+  int32_t profile;             /* 1: time kernel classes with HIP events        */
+  void *hip_stream;            /* hipStream_t to use, or NULL for an own stream */
+} td_options;
+
+/* Statistics of the initialisation. */
+typedef struct {
+  int32_t n_atoms, n_orb, n_pad;      /* n_pad: padded matrix dimension      */
+  int32_t inverse_iterations;         /* Newton-Schulz steps for S^-1        */
+  double inverse_residual;            /* max |1 - S S^-1| at exit            */
+  int32_t scc_iterations;             /* 0 when rho0 was given               */
+  double scc_residual;                /* max |dq_out - dq_in| at exit        */
+  int32_t purification_iterations;    /* in the last SCC cycle               */
+  double purification_error;          /* Tr(X) - Tr(X^2) at exit             */
+  double spectrum_lo, spectrum_hi;    /* bounds of the S^-1 H spectrum       */
+  int64_t step;                       /* index of the current rho            */
+  int32_t has_prev;                   /* 0: next step is an Euler start      */
+  int32_t precision;
+} td_info;
+
+/* Kernel classes timed when td_options.profile = 1. */
+enum {
+  TD_KT_GEMM_SH = 0,      /* S^-1 H product                 (2 n^3 flop) */
+  TD_KT_GEMM_ARHO = 1,    /* (S^-1 H) [Re rho | Im rho]     (4 n^3 flop) */
+  TD_KT_UPDATE = 2,       /* leapfrog update                             */
+  TD_KT_OTHER = 3,        /* charges, potential, H assembly, dipole      */
+  TD_KT_COUNT = 4
+};
+
+/* Fills *opt with defaults: FP64, 4 slices, dt = 0.2, scc_tol = 1e-12,
+ * scc_maxiter = 300, mix_beta = 0.3, mix_history = 8, profile = 0, own
+ * stream. */
+TD_API void td_default_options(td_options *opt);
+
+/* Creates a context (Sec. 2.3): copies the model to the GPU, forms S^-1,
+ * and either takes rho0 or solves the SCC ground state (Sec. 2.1) by
+ * density-matrix purification. The ground state is the initial density
+ * with no leapfrog history. On failure *out is NULL and err (if not NULL)
+ * receives a message of at most errlen bytes. */
+TD_API td_status td_create(const td_system *sys, const td_options *opt, td_ctx **out,
+                           char *err, int32_t errlen);
+
+/* Applies a delta pulse E(t) = e0 delta(t) dir to the current rho
+ * (Sec. 2.2, Eq. 16). dir need not be normalised (non-zero). Clears the
+ * leapfrog history: the next step is an Euler start. */
+TD_API td_status td_kick(td_ctx *ctx, double e0, const double dir[3]);
+
+/* Advances n >= 0 steps of dt (Sec. 2.3, Eq. 19). field is NULL (no
+ * field) or [n * 3]: field[3k..3k+2] = E(t) at the time of the k-th
+ * density matrix of this call. The dipole of each density entering a
+ * step is recorded (see td_get_dipole_series). Returns TD_EUNSTABLE if
+ * the state became non-finite. */
+TD_API td_status td_step(td_ctx *ctx, int32_t n, const double *field);
+
+/* Mulliken charge fluctuations dq [n_atoms] of the current rho (Eq. 5). */
+TD_API td_status td_get_charges(td_ctx *ctx, double *dq);
+
+/* Mulliken dipole mu[3] of the current rho. */
+TD_API td_status td_get_dipole(td_ctx *ctx, double mu[3]);
+
+/* Dipoles recorded by the last td_step: mu[3k..3k+2] for the k-th step,
+ * k < min(cap, n); *n_out = number recorded by that call. */
+TD_API td_status td_get_dipole_series(td_ctx *ctx, double *mu, int32_t cap, int32_t *n_out);
+
+/* Energy of the current rho: Re Tr(rho H0) + 1/2 dq gamma dq
+ * + sum_A dq_A R_A . field (field may be NULL for zero) (Sec. 2.1,
+ * Eqs. 2-3). */
+TD_API td_status td_get_energy(td_ctx *ctx, const double field[3], double *energy);
+
+/* Checkpoint: current and previous density matrices as [n_orb * n_orb]
+ * interleaved complex128 (rho_prev may be NULL), the step index and
+ * whether a previous density exists. */
+TD_API td_status td_get_rho(td_ctx *ctx, double *rho, double *rho_prev, int64_t *step,
+                            int32_t *has_prev);
+
+/* Restore: rho (required) and rho_prev (NULL: next step is an Euler start),
+ * both [n_orb * n_orb] interleaved complex128; step is the index of rho. */
+TD_API td_status td_set_rho(td_ctx *ctx, const double *rho, const double *rho_prev,
+                            int64_t step);
+
+TD_API td_status td_get_info(td_ctx *ctx, td_info *info);
+
+/* Accumulated HIP-event time (ms) and launch count of a kernel class
+ * since creation or the last reset (needs td_options.profile = 1). */
+TD_API td_status td_get_kernel_time(td_ctx *ctx, int32_t kind, double *total_ms,
+                                    int64_t *launches);
+TD_API td_status td_reset_kernel_time(td_ctx *ctx);
+
+/* Ehrenfest forces (Sec. 2.1, Eq. 15): not available with clamped nuclei;
+ * returns TD_ENOTSUP. */
+TD_API td_status td_get_forces(td_ctx *ctx, double *forces);
+
+TD_API const char *td_last_error(const td_ctx *ctx);
+TD_API const char *td_status_string(int32_t status);
+TD_API void td_destroy(td_ctx *ctx);
+
+/* Dense product C = A B (row-major, A [m x k], B [k x n], C [m x n]) on
+ * the GPU with the library's propagation kernels in the given precision:
+ * the matrix-product building block of the step (Sec. 2.3). Host
+ * pointers; err receives a message on failure. */
+TD_API td_status td_util_gemm(int32_t precision, int32_t n_slices, int32_t m, int32_t n,
+                              int32_t k, const double *A, const double *B, double *C,
+                              char *err, int32_t errlen);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDDFTB_H */

@@ -46,7 +46,7 @@ C_AU = 137.035999084   # speed of light in atomic units
 
 __all__ = [
     "atom_of_orbital", "mulliken_populations", "charge_fluctuations",
-    "external_potential", "scc_hamiltonian", "scc_hamiltonian_fast", "inverse_overlap", "rho_dot",
+    "external_potential", "scc_hamiltonian", "scc_hamiltonian_fast", "inverse_overlap", "rho_dot", "rho_dot_rows",
     "euler_step", "leapfrog_step", "kick", "dipole", "energy", "electron_count",
     "GroundState", "ground_state", "Trajectory", "propagate",
     "polarizability", "cross_section", "stationarity_residual",
@@ -123,6 +123,18 @@ def rho_dot(rho, H, Sinv):
     SinvH = Sinv @ H
     HSinv = H @ Sinv
     return -1j * (SinvH @ rho - rho @ HSinv)
+
+
+def rho_dot_rows(rho, H, Sinv, rows):
+    """Selected rows of Eq. 10 (D = 0): rhodot[i, :] for i in ``rows``.
+
+    (S^-1 H)[i, :] = S^-1[i, :] H and (rho H S^-1)[i, :] = (rho[i, :] H) S^-1,
+    each O(n^2) per row, so single rows are checkable at any size.
+    """
+    rows = np.asarray(rows)
+    a = Sinv[rows, :] @ H
+    b = (rho[rows, :] @ H) @ Sinv
+    return -1j * (a @ rho - b)
 
 
 def euler_step(rho, rhodot, dt):

@@ -1,0 +1,110 @@
+// Shared declarations of the TD-DFTB HIP library (device launchers and
+// host helpers). Every launcher enqueues work on the given stream and
+// returns the launch status; none synchronises.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace td {
+
+// Macro tile of the FP64 matrix-core product. Matrix dimensions handed to
+// the product kernels are multiples of it; the library pads every matrix
+// to a multiple of kPad with zeros.
+constexpr int kGemmTile = 128;
+constexpr int kPad = 128;
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// ---------------------------------------------------------------- products
+// C[m x n] = alpha * A[m x k] B[k x n] + beta * Cin, row-major, leading
+// dimensions in elements; m, n multiples of kGemmTile, k multiple of 16.
+// `tag` only selects a separately named kernel instance (so profilers
+// separate the two products of a step): 0 generic, 1 S^-1 H, 2 A rho.
+hipError_t dgemm(hipStream_t s, int tag, int m, int n, int k, double alpha,
+                 const double* A, int lda, const double* B, int ldb, double beta,
+                 const double* Cin, int ldcin, double* C, int ldc);
+
+// ---------------------------------------------------------------- O(n^2) kernels
+// out[r] = sum_c X[r, c] * Y[r, c] for r < rows (cols multiple of 2).
+hipError_t rowdot(hipStream_t s, const double* X, int ldx, const double* Y, int ldy,
+                  double* out, int rows, int cols);
+
+// dq[a] = sum_{u in a} q_orb[u] - q0[a]; mu = -sum_a dq[a] R_a -> mu_out[3];
+// electrons (sum of q_orb) -> ne_out (may be null).
+hipError_t charges_dipole(hipStream_t s, const double* q_orb, const int* orb_off,
+                          const double* q0, const double* pos, int na, double* dq,
+                          double* mu_out, double* ne_out);
+
+// v[a] = sum_c gamma[a, c] dq[c] + R_a . E (E may be null); vorb[u] = v[atom(u)].
+hipError_t potential(hipStream_t s, const double* gamma, const double* dq,
+                     const double* pos, const double* E, const int* orb_off, int na,
+                     double* v, double* vorb);
+
+// H = H0 + 1/2 S o (vorb_u + vorb_v), n x n with leading dimension n.
+hipError_t assemble_h(hipStream_t s, const double* H0, const double* S, const double* vorb,
+                      double* H, int n);
+
+// Transpose-pair passes over np x np tiles (np multiple of 32):
+//  leapfrog:   out = base + f * rhodot with rhodot = -i (X - X^+),
+//              X = Xre + i Xim:  Re rhodot = Xim + Xim^T,  Im rhodot = Xre^T - Xre
+//  herm:       out = (T + T^+) / 2
+//  sym:        out_re = (T + T^T) / 2 (real), out_im = 0 when given
+hipError_t pair_leapfrog(hipStream_t s, const double* xre, const double* xim, int ldx,
+                         const double* bre, const double* bim, int ldb, double* ore,
+                         double* oim, int ldo, int np, double f);
+hipError_t pair_herm(hipStream_t s, const double* tre, const double* tim, int ldt,
+                     double* ore, double* oim, int ldo, int np);
+hipError_t pair_sym(hipStream_t s, const double* t, int ldt, double* ore, double* oim,
+                    int ldo, int np);
+
+// (re, im)[u, v] *= exp(-i kappa (x_u - x_v)).
+hipError_t kick_phase(hipStream_t s, double* re, double* im, int ld, const double* x,
+                      int np, double kappa);
+
+// X = c * I on the first n diagonal entries, zero elsewhere (np x np, ld np).
+hipError_t scaled_identity(hipStream_t s, double* X, int np, int n, double c);
+// T = 2 I_n - T (np x np).
+hipError_t two_minus(hipStream_t s, double* T, int np, int n);
+// X = (emax I_n - T) / (emax - emin).
+hipError_t sp2_init(hipStream_t s, const double* T, double* X, int np, int n, double emax,
+                    double emin);
+// mode 0: X = X2; mode 1: X = 2 X - X2.
+hipError_t sp2_update(hipStream_t s, double* X, const double* X2, int np, int mode);
+// Copy a real np x np matrix (ld ldr) into the real block of a wide matrix, zero imag.
+hipError_t real_to_wide(hipStream_t s, const double* R, int ldr, double* W, int np);
+// Interleaved complex [n x n] <-> wide planar [np x 2np] (re | im).
+hipError_t interleaved_to_wide(hipStream_t s, const double* Z, int n, double* W, int np);
+hipError_t wide_to_interleaved(hipStream_t s, const double* W, int np, double* Z, int n);
+// Plain real copy with padding: dst[np x np] <- src[n x n] (rest zero beforehand).
+hipError_t pad_copy(hipStream_t s, const double* src, int n, double* dst, int np);
+hipError_t unpad_copy(hipStream_t s, const double* src, int np, double* dst, int n);
+
+// ---------------------------------------------------------------- reductions
+// out[0] = sum_i X[i, i], i < n.
+hipError_t trace(hipStream_t s, const double* X, int ld, int n, double* out);
+// out[0] = max_{i,j<n} |delta_ij - T_ij| (work: n doubles).
+hipError_t identity_residual(hipStream_t s, const double* T, int ld, int n, double* work,
+                             double* out);
+// Gershgorin bounds of T (n x n): out[0] = min(center - radius), out[1] = max(...).
+hipError_t gershgorin(hipStream_t s, const double* T, int ld, int n, double* work_lo,
+                      double* work_hi, double* out);
+// out[0] = sum_i x[i]
+hipError_t sum_vector(hipStream_t s, const double* x, int n, double* out);
+
+// Anderson mixing of SCC charges: r = dq_out - dq_in, out_resid[0] = max|r|;
+// history slot `slot` <- (dq_in, r); `count` valid entries after storing;
+// dq_in <- Anderson update with parameter beta.
+hipError_t anderson_mix(hipStream_t s, double* dq_in, const double* dq_out, double* hx,
+                        double* hf, int na, int m, int count, int slot, double beta,
+                        double* out_resid);
+
+// Energy pieces of the current state: out[0] = sum R o H0 (work: rows),
+// out[1] = 1/2 dq gamma dq, out[2] = sum dq_a R_a . E (E may be null).
+hipError_t energy_terms(hipStream_t s, const double* q_band_rows, int n, const double* dq,
+                        const double* v_gamma, const double* pos, const double* E, int na,
+                        double* out);
+
+}  // namespace td

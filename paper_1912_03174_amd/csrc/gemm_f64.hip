@@ -1,0 +1,173 @@
+// FP64 matrix-core product C = alpha A B + beta Cin for the density-matrix
+// step (the S^-1 H and (S^-1 H)[Re rho | Im rho] products of Sec. 2.3).
+//
+// gfx950 design:
+//  * 128 x 128 macro tile per 256-thread workgroup, four 64-wide waves in
+//    a 2 x 2 grid, each wave owning a 64 x 64 sub-tile = 4 x 4 blocks of
+//    v_mfma_f64_16x16x4_f64 (16 double4 accumulators per lane).
+//  * K advances 16 per stage. Tiles of A (stored k-major, so one MFMA
+//    operand fetch is 16 consecutive doubles per k row) and B are staged
+//    in LDS with double buffering: the next stage's global loads are in
+//    flight in registers while the matrix cores work on the current one;
+//    one barrier per stage. 66.5 KB of LDS per workgroup, two per CU.
+//  * Workgroups are dispatched round-robin over the 8 XCDs; the block id
+//    is remapped so each XCD owns a contiguous range of tiles, ordered in
+//    groups of 8 tile rows, so concurrently running tiles on one XCD share
+//    A and B panels in that XCD's L2.
+#include "common.hpp"
+
+namespace td {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128;
+constexpr int BN = 128;
+constexpr int BK = 16;
+constexpr int PAD = 2;
+constexpr int LDA_S = BM + PAD;   // As[k][m]
+constexpr int LDB_S = BN + PAD;   // Bs[k][n]
+constexpr int GROUP_M = 8;
+
+template <int TAG>
+__global__ __launch_bounds__(256) void dgemm_nn(const double* __restrict__ A, int lda,
+                                                const double* __restrict__ B, int ldb,
+                                                double* C, int ldc, const double* Cin,
+                                                int ldcin, int K, double alpha, double beta,
+                                                int tiles_m, int tiles_n) {
+  __shared__ double As[2][BK][LDA_S];
+  __shared__ double Bs[2][BK][LDB_S];
+
+  // XCD-aware tile order: blocks w with w % 8 == x run on XCD x.
+  const int nt = tiles_m * tiles_n;
+  const int w = blockIdx.x;
+  const int q = nt >> 3, r = nt & 7;
+  const int xcd = w & 7, slot = w >> 3;
+  const int lin = xcd * q + (xcd < r ? xcd : r) + slot;
+  const int group = GROUP_M * tiles_n;
+  const int g = lin / group;
+  const int first_m = g * GROUP_M;
+  const int gsz = (tiles_m - first_m) < GROUP_M ? (tiles_m - first_m) : GROUP_M;
+  const int in_g = lin - g * group;
+  const int tm = first_m + in_g % gsz;
+  const int tn = in_g / gsz;
+  const int m0 = tm * BM, n0 = tn * BN;
+
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+
+  // Global -> register mapping: A rows (t>>1), 8 consecutive k at (t&1)*8;
+  // B k row (t>>4), 8 consecutive n at (t&15)*8.
+  const int a_row = t >> 1, a_k = (t & 1) * 8;
+  const int b_k = t >> 4, b_n = (t & 15) * 8;
+  const double* Ag = A + (size_t)(m0 + a_row) * lda + a_k;
+  const double* Bg = B + (size_t)b_k * ldb + n0 + b_n;
+
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  double2 ra[4], rb[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    ra[i] = *reinterpret_cast<const double2*>(Ag + 2 * i);
+    rb[i] = *reinterpret_cast<const double2*>(Bg + 2 * i);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    As[0][a_k + 2 * i][a_row] = ra[i].x;
+    As[0][a_k + 2 * i + 1][a_row] = ra[i].y;
+    *reinterpret_cast<double2*>(&Bs[0][b_k][b_n + 2 * i]) = rb[i];
+  }
+  __syncthreads();
+
+  const int nk = K / BK;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = (kt + 1) < nk;
+    if (more) {
+      const double* an = Ag + (size_t)(kt + 1) * BK;
+      const double* bn = Bg + (size_t)(kt + 1) * BK * ldb;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        ra[i] = *reinterpret_cast<const double2*>(an + 2 * i);
+        rb[i] = *reinterpret_cast<const double2*>(bn + 2 * i);
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kl = kk + lk;
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[cur][kl][wm * 64 + i * 16 + l16];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[cur][kl][wn * 64 + j * 16 + l16];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+      const int nxt = cur ^ 1;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        As[nxt][a_k + 2 * i][a_row] = ra[i].x;
+        As[nxt][a_k + 2 * i + 1][a_row] = ra[i].y;
+        *reinterpret_cast<double2*>(&Bs[nxt][b_k][b_n + 2 * i]) = rb[i];
+      }
+    }
+    __syncthreads();
+  }
+
+  // Accumulator layout of the 16x16 f64 block: lane holds rows 4*(lane/16)+r,
+  // column lane%16, r = 0..3.
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = n0 + wn * 64 + j * 16 + l16;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int row = m0 + wm * 64 + i * 16 + lk * 4 + rr;
+        double v = alpha * acc[i][j][rr];
+        if (beta != 0.0) v += beta * Cin[(size_t)row * ldcin + col];
+        C[(size_t)row * ldc + col] = v;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t dgemm(hipStream_t s, int tag, int m, int n, int k, double alpha, const double* A,
+                 int lda, const double* B, int ldb, double beta, const double* Cin, int ldcin,
+                 double* C, int ldc) {
+  if (m % BM || n % BN || k % BK || m <= 0 || n <= 0 || k <= 0) return hipErrorInvalidValue;
+  if (lda % 2 || ldb % 2 || lda < k || ldb < n || ldc < n) return hipErrorInvalidValue;
+  if (beta != 0.0 && (Cin == nullptr || ldcin < n)) return hipErrorInvalidValue;
+  const int tm = m / BM, tn = n / BN;
+  const dim3 grid(tm * tn), block(256);
+  switch (tag) {
+    case 1:
+      hipLaunchKernelGGL(dgemm_nn<1>, grid, block, 0, s, A, lda, B, ldb, C, ldc, Cin, ldcin, k,
+                         alpha, beta, tm, tn);
+      break;
+    case 2:
+      hipLaunchKernelGGL(dgemm_nn<2>, grid, block, 0, s, A, lda, B, ldb, C, ldc, Cin, ldcin, k,
+                         alpha, beta, tm, tn);
+      break;
+    default:
+      hipLaunchKernelGGL(dgemm_nn<0>, grid, block, 0, s, A, lda, B, ldb, C, ldc, Cin, ldcin, k,
+                         alpha, beta, tm, tn);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace td

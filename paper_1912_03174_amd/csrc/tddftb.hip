@@ -1,0 +1,709 @@
+// C ABI of the TD-DFTB propagation library (declared in tddftb.h).
+//
+// Device layout (all float64, row-major, dimension padded to np, a
+// multiple of 128, with zeros outside the n x n block):
+//   S, H0, S^-1, H, A = S^-1 H           np x np
+//   rho_cur, rho_prev, X = A rho         np x 2np "wide" planar complex:
+//                                        columns [0, np) real part,
+//                                        columns [np, 2np) imaginary part
+// so that A [Re rho | Im rho] is one real product with 2np columns, and
+// the zero padding keeps every product and update exact on the n x n
+// block without tail handling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tddftb.h"
+#include "common.hpp"
+
+using td::round_up;
+
+struct td_ctx {
+  int na = 0, n = 0, np = 0, nelec = 0;
+  td_options opt{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  double *S = nullptr, *H0 = nullptr, *Sinv = nullptr, *H = nullptr, *A = nullptr;
+  double *rho_cur = nullptr, *rho_prev = nullptr, *X = nullptr;
+  double *gamma = nullptr, *pos = nullptr, *q0 = nullptr;
+  int* orb_off = nullptr;
+  double *q_orb = nullptr, *dq = nullptr, *dq_in = nullptr, *v = nullptr, *vorb = nullptr;
+  double *xorb = nullptr, *work1 = nullptr, *work2 = nullptr, *scal = nullptr;
+  double *hx = nullptr, *hf = nullptr;
+  double* field = nullptr;
+  int field_cap = 0;
+  double* dip = nullptr;
+  int dip_cap = 0;
+  std::vector<int> orb_off_h;
+  std::vector<double> pos_h;
+  std::vector<double> dq_h;
+  double mu_h[3] = {0, 0, 0};
+  int64_t step = 0;
+  bool has_prev = false;
+  int last_n = 0;
+  td_info info{};
+  std::string err;
+  // profiling
+  std::vector<hipEvent_t> ev;
+  double kt_ms[TD_KT_COUNT] = {0, 0, 0, 0};
+  int64_t kt_n[TD_KT_COUNT] = {0, 0, 0, 0};
+};
+
+namespace {
+
+// scal[] slots
+enum { SC_MU = 0, SC_NE = 3, SC_RES = 4, SC_TR1 = 5, SC_TR2 = 6, SC_BOUNDS = 8, SC_E = 10,
+       SC_FIELD = 16, SC_COUNT = 32 };
+
+struct Fail {
+  td_status st;
+};
+
+void set_err(char* buf, int len, const std::string& m) {
+  if (buf && len > 0) {
+    std::snprintf(buf, (size_t)len, "%s", m.c_str());
+  }
+}
+
+#define HIPCHK(ctx, expr)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);                       \
+      throw Fail{e_ == hipErrorOutOfMemory ? TD_ENOMEM : TD_EHIP};                          \
+    }                                                                                       \
+  } while (0)
+
+#define REQUIRE(ctx, cond, status, msg) \
+  do {                                  \
+    if (!(cond)) {                      \
+      (ctx)->err = (msg);               \
+      throw Fail{status};               \
+    }                                   \
+  } while (0)
+
+template <class F>
+td_status guarded(td_ctx* ctx, F&& f) {
+  if (!ctx) return TD_EINVAL;
+  try {
+    ctx->err.clear();
+    f();
+    return TD_OK;
+  } catch (const Fail& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "host allocation failed";
+    return TD_ENOMEM;
+  } catch (...) {
+    ctx->err = "unexpected internal error";
+    return TD_EHIP;
+  }
+}
+
+void dalloc(td_ctx* c, double** p, size_t count) {
+  HIPCHK(c, hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(double)));
+  HIPCHK(c, hipMemsetAsync(*p, 0, std::max<size_t>(count, 1) * sizeof(double), c->stream));
+}
+
+void free_all(td_ctx* c) {
+  double** bufs[] = {&c->S,   &c->H0,   &c->Sinv, &c->H,     &c->A,    &c->rho_cur,
+                     &c->rho_prev, &c->X, &c->gamma, &c->pos, &c->q0, &c->q_orb,
+                     &c->dq,  &c->dq_in, &c->v,   &c->vorb,  &c->xorb, &c->work1,
+                     &c->work2, &c->scal, &c->hx, &c->hf,    &c->field, &c->dip};
+  for (double** b : bufs) {
+    if (*b) hipFree(*b);
+    *b = nullptr;
+  }
+  if (c->orb_off) hipFree(c->orb_off);
+  c->orb_off = nullptr;
+  for (hipEvent_t e : c->ev) hipEventDestroy(e);
+  c->ev.clear();
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  c->stream = nullptr;
+}
+
+void sync(td_ctx* c) { HIPCHK(c, hipStreamSynchronize(c->stream)); }
+
+void read_scal(td_ctx* c, int slot, double* out, int count) {
+  HIPCHK(c, hipMemcpyAsync(out, c->scal + slot, sizeof(double) * count, hipMemcpyDeviceToHost,
+                           c->stream));
+  sync(c);
+}
+
+void gemm(td_ctx* c, int tag, int m, int n, int k, double alpha, const double* A, int lda,
+          const double* B, int ldb, double* C, int ldc) {
+  HIPCHK(c, td::dgemm(c->stream, tag, m, n, k, alpha, A, lda, B, ldb, 0.0, nullptr, 0, C, ldc));
+}
+
+// Mulliken charges, dipole and electron count of rho_cur; dipole -> `mu`
+// (device, 3 doubles).
+void mulliken(td_ctx* c, double* mu) {
+  HIPCHK(c, td::rowdot(c->stream, c->rho_cur, 2 * c->np, c->S, c->np, c->q_orb, c->np, c->np));
+  HIPCHK(c, td::charges_dipole(c->stream, c->q_orb, c->orb_off, c->q0, c->pos, c->na, c->dq, mu,
+                               c->scal + SC_NE));
+}
+
+// Observables of the current state, copied to the host; checks finiteness.
+void refresh(td_ctx* c) {
+  mulliken(c, c->scal + SC_MU);
+  c->dq_h.resize(c->na);
+  HIPCHK(c, hipMemcpyAsync(c->dq_h.data(), c->dq, sizeof(double) * c->na, hipMemcpyDeviceToHost,
+                           c->stream));
+  read_scal(c, SC_MU, c->mu_h, 3);
+  bool ok = std::isfinite(c->mu_h[0]) && std::isfinite(c->mu_h[1]) && std::isfinite(c->mu_h[2]);
+  for (int a = 0; a < c->na && ok; ++a) ok = std::isfinite(c->dq_h[a]);
+  REQUIRE(c, ok, TD_EUNSTABLE, "density matrix became non-finite (time step too large?)");
+}
+
+// S^-1 by the Newton-Schulz iteration X <- X (2 - S X), X_0 = I / g with g
+// a Gershgorin bound of the largest eigenvalue of S.
+void inverse_overlap(td_ctx* c) {
+  const int n = c->n, np = c->np;
+  HIPCHK(c, td::gershgorin(c->stream, c->S, np, n, c->work1, c->work2, c->scal + SC_BOUNDS));
+  double b[2];
+  read_scal(c, SC_BOUNDS, b, 2);
+  REQUIRE(c, std::isfinite(b[1]) && b[1] > 0, TD_ENOTPOSDEF, "S has no positive spectrum bound");
+  HIPCHK(c, td::scaled_identity(c->stream, c->Sinv, np, n, 1.0 / b[1]));
+  double prev = INFINITY, res = INFINITY;
+  int it = 0;
+  for (it = 1; it <= 200; ++it) {
+    gemm(c, 0, np, np, np, 1.0, c->S, np, c->Sinv, np, c->A, np);     // T = S X
+    HIPCHK(c, td::identity_residual(c->stream, c->A, np, n, c->work1, c->scal + SC_RES));
+    read_scal(c, SC_RES, &res, 1);
+    REQUIRE(c, std::isfinite(res) && res < 1e3, TD_ENOTPOSDEF,
+            "S is not positive definite: inverse iteration diverged");
+    if (res < 1e-15 || (res < 1e-9 && res >= 0.5 * prev)) break;
+    prev = res;
+    HIPCHK(c, td::two_minus(c->stream, c->A, np, n));                   // 2 - S X
+    gemm(c, 0, np, np, np, 1.0, c->Sinv, np, c->A, np, c->H, np);       // X (2 - S X)
+    std::swap(c->Sinv, c->H);
+  }
+  REQUIRE(c, res < 1e-8, TD_ENOTPOSDEF, "S is singular or indefinite: inverse did not converge");
+  HIPCHK(c, td::pair_sym(c->stream, c->Sinv, np, c->Sinv, nullptr, np, np));
+  c->info.inverse_iterations = it;
+  c->info.inverse_residual = res;
+}
+
+// Zero-temperature density by second-order spectral projection (SP2,
+// Niklasson, Phys. Rev. B 66, 155115 (2002)) of T = S^-1 H: X_0 maps the
+// spectrum into [0, 1] reversed, X <- X^2 or 2X - X^2 steers Tr X to the
+// number of occupied states; rho = 2 X S^-1. Input H in c->H; output the
+// real density in the real block of rho_cur.
+void purify(td_ctx* c) {
+  const int n = c->n, np = c->np;
+  const double nocc = 0.5 * c->nelec;
+  gemm(c, 0, np, np, np, 1.0, c->Sinv, np, c->H, np, c->A, np);        // T = S^-1 H
+  HIPCHK(c, td::gershgorin(c->stream, c->A, np, n, c->work1, c->work2, c->scal + SC_BOUNDS));
+  double b[2];
+  read_scal(c, SC_BOUNDS, b, 2);
+  REQUIRE(c, std::isfinite(b[0]) && std::isfinite(b[1]) && b[1] > b[0], TD_ESCF,
+          "invalid spectrum bounds of S^-1 H");
+  c->info.spectrum_lo = b[0];
+  c->info.spectrum_hi = b[1];
+  double* Xm = c->H;          // H is consumed by T
+  double* X2 = c->rho_prev;   // scratch (np x np view)
+  HIPCHK(c, td::sp2_init(c->stream, c->A, Xm, np, n, b[1], b[0]));
+  double prev = INFINITY, err = INFINITY;
+  int it;
+  for (it = 1; it <= 400; ++it) {
+    gemm(c, 0, np, np, np, 1.0, Xm, np, Xm, np, X2, np);
+    HIPCHK(c, td::trace(c->stream, Xm, np, n, c->scal + SC_TR1));
+    HIPCHK(c, td::trace(c->stream, X2, np, n, c->scal + SC_TR2));
+    double tr[2];
+    read_scal(c, SC_TR1, tr, 2);
+    err = tr[0] - tr[1];
+    REQUIRE(c, std::isfinite(err), TD_ESCF, "purification produced non-finite values");
+    const int mode = (std::fabs(tr[1] - nocc) < std::fabs(2.0 * tr[0] - tr[1] - nocc)) ? 0 : 1;
+    HIPCHK(c, td::sp2_update(c->stream, Xm, X2, np, mode));
+    if (std::fabs(err) < 1e-5 && std::fabs(err) >= prev) break;
+    prev = std::fabs(err);
+  }
+  REQUIRE(c, it <= 400 && std::fabs(err) < 1e-6, TD_ESCF,
+          "purification did not converge (HOMO-LUMO gap too small?)");
+  c->info.purification_iterations = it;
+  c->info.purification_error = err;
+  gemm(c, 0, np, np, np, 2.0, Xm, np, c->Sinv, np, X2, np);            // rho = 2 X S^-1
+  HIPCHK(c, td::pair_sym(c->stream, X2, np, c->rho_cur, c->rho_cur + np, 2 * np, np));
+}
+
+void ground_state(td_ctx* c) {
+  const int na = c->na, np = c->np;
+  const int m = std::max(1, std::min(8, c->opt.mix_history));
+  HIPCHK(c, hipMemsetAsync(c->dq_in, 0, sizeof(double) * na, c->stream));
+  double res = INFINITY;
+  int it;
+  for (it = 1; it <= c->opt.scc_maxiter; ++it) {
+    HIPCHK(c, td::potential(c->stream, c->gamma, c->dq_in, c->pos, nullptr, c->orb_off, na, c->v,
+                            c->vorb));
+    HIPCHK(c, td::assemble_h(c->stream, c->H0, c->S, c->vorb, c->H, np));
+    purify(c);
+    mulliken(c, c->scal + SC_MU);
+    const int count = std::min(it, m), slot = (it - 1) % m;
+    HIPCHK(c, td::anderson_mix(c->stream, c->dq_in, c->dq, c->hx, c->hf, na, m, count, slot,
+                               c->opt.mix_beta, c->scal + SC_RES));
+    read_scal(c, SC_RES, &res, 1);
+    REQUIRE(c, std::isfinite(res), TD_ESCF, "SCC cycle produced non-finite charges");
+    if (res < c->opt.scc_tol) break;
+  }
+  c->info.scc_iterations = std::min(it, c->opt.scc_maxiter);
+  c->info.scc_residual = res;
+  REQUIRE(c, res < c->opt.scc_tol, TD_ESCF, "SCC ground state did not converge");
+}
+
+void ensure_events(td_ctx* c, size_t count) {
+  while (c->ev.size() < count) {
+    hipEvent_t e;
+    HIPCHK(c, hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+void validate(td_ctx* c, const td_system* s, const td_options* o) {
+  REQUIRE(c, s && o, TD_EINVAL, "null system or options");
+  REQUIRE(c, s->n_atoms > 0 && s->n_orb > 0, TD_EINVAL, "n_atoms and n_orb must be positive");
+  REQUIRE(c, s->n_orb <= 65536, TD_EINVAL, "n_orb too large");
+  REQUIRE(c, s->orb_offset && s->positions && s->S && s->H0 && s->gamma && s->q0, TD_EINVAL,
+          "null array in td_system");
+  REQUIRE(c, s->orb_offset[0] == 0 && s->orb_offset[s->n_atoms] == s->n_orb, TD_EINVAL,
+          "orb_offset must start at 0 and end at n_orb");
+  for (int a = 0; a < s->n_atoms; ++a)
+    REQUIRE(c, s->orb_offset[a + 1] > s->orb_offset[a], TD_EINVAL,
+            "orb_offset must be strictly increasing");
+  REQUIRE(c, s->n_elec > 0 && s->n_elec % 2 == 0 && s->n_elec <= 2 * s->n_orb, TD_EINVAL,
+          "n_elec must be even and in (0, 2 n_orb]");
+  REQUIRE(c, o->dt > 0 && std::isfinite(o->dt), TD_EINVAL, "dt must be positive");
+  REQUIRE(c, o->precision == TD_FP64 || o->precision == TD_SPLIT_BF16, TD_EINVAL,
+          "unknown precision");
+  REQUIRE(c, o->precision == TD_FP64, TD_ENOTSUP, "split-bf16 precision is not available");
+  REQUIRE(c, o->scc_tol > 0 && o->scc_maxiter > 0 && o->mix_beta > 0 && o->mix_beta <= 1,
+          TD_EINVAL, "invalid SCC options");
+  const size_t n = (size_t)s->n_orb, na = (size_t)s->n_atoms;
+  REQUIRE(c, finite_all(s->S, n * n) && finite_all(s->H0, n * n) &&
+                 finite_all(s->gamma, na * na) && finite_all(s->q0, na) &&
+                 finite_all(s->positions, na * 3),
+          TD_EINVAL, "non-finite input values");
+  double smax = 0.0, asym = 0.0;
+  for (size_t i = 0; i < n; ++i)
+    for (size_t j = i + 1; j < n; ++j) {
+      smax = std::max(smax, std::fabs(s->S[i * n + j]));
+      asym = std::max(asym, std::fabs(s->S[i * n + j] - s->S[j * n + i]));
+      asym = std::max(asym, std::fabs(s->H0[i * n + j] - s->H0[j * n + i]));
+    }
+  REQUIRE(c, asym <= 1e-12, TD_EINVAL, "S and H0 must be symmetric");
+  if (s->rho0) REQUIRE(c, finite_all(s->rho0, 2 * n * n), TD_EINVAL, "non-finite rho0");
+}
+
+void upload_padded(td_ctx* c, const double* host, int n, double* dev, int np) {
+  HIPCHK(c, hipMemcpy2DAsync(dev, sizeof(double) * np, host, sizeof(double) * n,
+                             sizeof(double) * n, n, hipMemcpyHostToDevice, c->stream));
+}
+
+void create_impl(td_ctx* c, const td_system* s, const td_options* o) {
+  validate(c, s, o);
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  REQUIRE(c, e == hipSuccess && ndev > 0, TD_EHIP,
+          std::string("no HIP device available: ") + hipGetErrorString(e));
+  c->opt = *o;
+  c->na = s->n_atoms;
+  c->n = s->n_orb;
+  c->np = round_up(s->n_orb, td::kPad);
+  c->nelec = s->n_elec;
+  const int na = c->na, n = c->n, np = c->np;
+  if (o->hip_stream) {
+    c->stream = (hipStream_t)o->hip_stream;
+  } else {
+    HIPCHK(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  const size_t m2 = (size_t)np * np;
+  dalloc(c, &c->S, m2);
+  dalloc(c, &c->H0, m2);
+  dalloc(c, &c->Sinv, m2);
+  dalloc(c, &c->H, m2);
+  dalloc(c, &c->A, m2);
+  dalloc(c, &c->rho_cur, 2 * m2);
+  dalloc(c, &c->rho_prev, 2 * m2);
+  dalloc(c, &c->X, 2 * m2);
+  dalloc(c, &c->gamma, (size_t)na * na);
+  dalloc(c, &c->pos, (size_t)na * 3);
+  dalloc(c, &c->q0, na);
+  dalloc(c, &c->q_orb, np);
+  dalloc(c, &c->dq, na);
+  dalloc(c, &c->dq_in, na);
+  dalloc(c, &c->v, na);
+  dalloc(c, &c->vorb, np);
+  dalloc(c, &c->xorb, np);
+  dalloc(c, &c->work1, np);
+  dalloc(c, &c->work2, np);
+  dalloc(c, &c->scal, SC_COUNT);
+  dalloc(c, &c->hx, (size_t)8 * na);
+  dalloc(c, &c->hf, (size_t)8 * na);
+  HIPCHK(c, hipMalloc((void**)&c->orb_off, sizeof(int) * (na + 1)));
+  c->orb_off_h.assign(s->orb_offset, s->orb_offset + na + 1);
+  c->pos_h.assign(s->positions, s->positions + 3 * na);
+  HIPCHK(c, hipMemcpyAsync(c->orb_off, s->orb_offset, sizeof(int) * (na + 1),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->pos, s->positions, sizeof(double) * 3 * na, hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->q0, s->q0, sizeof(double) * na, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->gamma, s->gamma, sizeof(double) * na * na, hipMemcpyHostToDevice,
+                           c->stream));
+  upload_padded(c, s->S, n, c->S, np);
+  upload_padded(c, s->H0, n, c->H0, np);
+  c->info.n_atoms = na;
+  c->info.n_orb = n;
+  c->info.n_pad = np;
+  c->info.precision = o->precision;
+  inverse_overlap(c);
+  if (s->rho0) {
+    HIPCHK(c, hipMemcpyAsync(c->X, s->rho0, sizeof(double) * 2 * (size_t)n * n,
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, td::interleaved_to_wide(c->stream, c->X, n, c->rho_cur, np));
+  } else {
+    ground_state(c);
+  }
+  c->step = 0;
+  c->has_prev = false;
+  refresh(c);
+}
+
+void step_impl(td_ctx* c, int nsteps, const double* field) {
+  REQUIRE(c, nsteps >= 0, TD_EINVAL, "n must be >= 0");
+  if (nsteps == 0) return;
+  if (field) REQUIRE(c, finite_all(field, 3 * (size_t)nsteps), TD_EINVAL, "non-finite field");
+  const int na = c->na, np = c->np;
+  if (field && c->field_cap < nsteps) {
+    if (c->field) hipFree(c->field);
+    c->field = nullptr;
+    c->field_cap = 0;
+    dalloc(c, &c->field, 3 * (size_t)nsteps);
+    c->field_cap = nsteps;
+  }
+  if (c->dip_cap < nsteps) {
+    if (c->dip) hipFree(c->dip);
+    c->dip = nullptr;
+    c->dip_cap = 0;
+    dalloc(c, &c->dip, 3 * (size_t)nsteps);
+    c->dip_cap = nsteps;
+  }
+  if (field)
+    HIPCHK(c, hipMemcpyAsync(c->field, field, sizeof(double) * 3 * nsteps, hipMemcpyHostToDevice,
+                             c->stream));
+  const bool prof = c->opt.profile != 0;
+  if (prof) ensure_events(c, 5 * (size_t)nsteps);
+  hipStream_t st = c->stream;
+  for (int k = 0; k < nsteps; ++k) {
+    hipEvent_t* e = prof ? &c->ev[5 * (size_t)k] : nullptr;
+    if (prof) HIPCHK(c, hipEventRecord(e[0], st));
+    // charges and dipole of rho_k, SCC potential, Hamiltonian (Eqs. 5-7)
+    mulliken(c, c->dip + 3 * (size_t)k);
+    HIPCHK(c, td::potential(st, c->gamma, c->dq, c->pos, field ? c->field + 3 * (size_t)k : nullptr,
+                            c->orb_off, na, c->v, c->vorb));
+    HIPCHK(c, td::assemble_h(st, c->H0, c->S, c->vorb, c->H, np));
+    if (prof) HIPCHK(c, hipEventRecord(e[1], st));
+    // X = S^-1 H rho (Eq. 10), as A = S^-1 H then A [Re rho | Im rho]
+    gemm(c, 1, np, np, np, 1.0, c->Sinv, np, c->H, np, c->A, np);
+    if (prof) HIPCHK(c, hipEventRecord(e[2], st));
+    gemm(c, 2, np, 2 * np, np, 1.0, c->A, np, c->rho_cur, 2 * np, c->X, 2 * np);
+    if (prof) HIPCHK(c, hipEventRecord(e[3], st));
+    // rho_{k+1} = rho_{k-1} + 2 dt rhodot (Eq. 19); Euler start without history
+    if (c->has_prev) {
+      HIPCHK(c, td::pair_leapfrog(st, c->X, c->X + np, 2 * np, c->rho_prev, c->rho_prev + np,
+                                  2 * np, c->rho_prev, c->rho_prev + np, 2 * np, np,
+                                  2.0 * c->opt.dt));
+    } else {
+      HIPCHK(c, td::pair_leapfrog(st, c->X, c->X + np, 2 * np, c->rho_cur, c->rho_cur + np,
+                                  2 * np, c->rho_prev, c->rho_prev + np, 2 * np, np, c->opt.dt));
+      c->has_prev = true;
+    }
+    std::swap(c->rho_cur, c->rho_prev);
+    if (prof) HIPCHK(c, hipEventRecord(e[4], st));
+    c->step += 1;
+  }
+  c->last_n = nsteps;
+  refresh(c);
+  if (prof) {
+    for (int k = 0; k < nsteps; ++k) {
+      hipEvent_t* e = &c->ev[5 * (size_t)k];
+      float ms[4];
+      HIPCHK(c, hipEventElapsedTime(&ms[0], e[0], e[1]));
+      HIPCHK(c, hipEventElapsedTime(&ms[1], e[1], e[2]));
+      HIPCHK(c, hipEventElapsedTime(&ms[2], e[2], e[3]));
+      HIPCHK(c, hipEventElapsedTime(&ms[3], e[3], e[4]));
+      c->kt_ms[TD_KT_OTHER] += ms[0];
+      c->kt_ms[TD_KT_GEMM_SH] += ms[1];
+      c->kt_ms[TD_KT_GEMM_ARHO] += ms[2];
+      c->kt_ms[TD_KT_UPDATE] += ms[3];
+      for (int q = 0; q < TD_KT_COUNT; ++q) c->kt_n[q] += 1;
+    }
+  }
+}
+
+void kick_impl(td_ctx* c, double e0, const double* dir) {
+  REQUIRE(c, dir && std::isfinite(e0), TD_EINVAL, "invalid kick arguments");
+  const double nrm = std::sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+  REQUIRE(c, nrm > 0 && std::isfinite(nrm), TD_EINVAL, "kick direction must be non-zero");
+  const int np = c->np;
+  std::vector<double> x(np, 0.0);
+  for (int a = 0; a < c->na; ++a) {
+    const double xa = (c->pos_h[3 * a] * dir[0] + c->pos_h[3 * a + 1] * dir[1] +
+                       c->pos_h[3 * a + 2] * dir[2]) / nrm;
+    for (int u = c->orb_off_h[a]; u < c->orb_off_h[a + 1]; ++u) x[u] = xa;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->xorb, x.data(), sizeof(double) * np, hipMemcpyHostToDevice,
+                           c->stream));
+  // rho(0+) = 1/2 (T + T^+), T = S^-1 K S rho K^+ (Sec. 2.2, Eq. 16)
+  gemm(c, 0, np, 2 * np, np, 1.0, c->S, np, c->rho_cur, 2 * np, c->X, 2 * np);
+  HIPCHK(c, td::kick_phase(c->stream, c->X, c->X + np, 2 * np, c->xorb, np, e0));
+  gemm(c, 0, np, 2 * np, np, 1.0, c->Sinv, np, c->X, 2 * np, c->rho_prev, 2 * np);
+  HIPCHK(c, td::pair_herm(c->stream, c->rho_prev, c->rho_prev + np, 2 * np, c->rho_cur,
+                          c->rho_cur + np, 2 * np, np));
+  c->has_prev = false;
+  sync(c);
+  refresh(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+void td_default_options(td_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = TD_FP64;
+  o->n_slices = 4;
+  o->dt = 0.2;
+  o->scc_tol = 1e-12;
+  o->scc_maxiter = 300;
+  o->mix_beta = 0.3;
+  o->mix_history = 8;
+  o->profile = 0;
+  o->hip_stream = nullptr;
+}
+
+td_status td_create(const td_system* sys, const td_options* opt, td_ctx** out, char* err,
+                    int32_t errlen) {
+  if (!out) {
+    set_err(err, errlen, "out must not be null");
+    return TD_EINVAL;
+  }
+  *out = nullptr;
+  td_ctx* c = new (std::nothrow) td_ctx();
+  if (!c) {
+    set_err(err, errlen, "host allocation failed");
+    return TD_ENOMEM;
+  }
+  td_status st = guarded(c, [&] { create_impl(c, sys, opt); });
+  if (st != TD_OK) {
+    set_err(err, errlen, c->err);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+    return st;
+  }
+  set_err(err, errlen, "");
+  *out = c;
+  return TD_OK;
+}
+
+td_status td_kick(td_ctx* ctx, double e0, const double dir[3]) {
+  return guarded(ctx, [&] { kick_impl(ctx, e0, dir); });
+}
+
+td_status td_step(td_ctx* ctx, int32_t n, const double* field) {
+  return guarded(ctx, [&] { step_impl(ctx, n, field); });
+}
+
+td_status td_get_charges(td_ctx* ctx, double* dq) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx, dq, TD_EINVAL, "null output");
+    std::memcpy(dq, ctx->dq_h.data(), sizeof(double) * ctx->na);
+  });
+}
+
+td_status td_get_dipole(td_ctx* ctx, double mu[3]) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx, mu, TD_EINVAL, "null output");
+    std::memcpy(mu, ctx->mu_h, sizeof(double) * 3);
+  });
+}
+
+td_status td_get_dipole_series(td_ctx* ctx, double* mu, int32_t cap, int32_t* n_out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx, n_out && cap >= 0 && (mu || cap == 0), TD_EINVAL, "invalid output");
+    const int k = std::min(cap, ctx->last_n);
+    if (k > 0)
+      HIPCHK(ctx, hipMemcpyAsync(mu, ctx->dip, sizeof(double) * 3 * k, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+    sync(ctx);
+    *n_out = ctx->last_n;
+  });
+}
+
+td_status td_get_energy(td_ctx* ctx, const double field[3], double* energy) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx, energy, TD_EINVAL, "null output");
+    td_ctx* c = ctx;
+    if (field)
+      HIPCHK(c, hipMemcpyAsync(c->scal + SC_FIELD, field, sizeof(double) * 3,
+                               hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, td::rowdot(c->stream, c->rho_cur, 2 * c->np, c->H0, c->np, c->work1, c->np, c->np));
+    HIPCHK(c, td::potential(c->stream, c->gamma, c->dq, c->pos, nullptr, c->orb_off, c->na, c->v,
+                            c->vorb));
+    HIPCHK(c, td::energy_terms(c->stream, c->work1, c->np, c->dq, c->v, c->pos,
+                               field ? c->scal + SC_FIELD : nullptr, c->na, c->scal + SC_E));
+    double e[3];
+    read_scal(c, SC_E, e, 3);
+    *energy = e[0] + e[1] + e[2];
+  });
+}
+
+td_status td_get_rho(td_ctx* ctx, double* rho, double* rho_prev, int64_t* step,
+                     int32_t* has_prev) {
+  return guarded(ctx, [&] {
+    td_ctx* c = ctx;
+    const size_t n2 = (size_t)c->n * c->n;
+    if (rho) {
+      HIPCHK(c, td::wide_to_interleaved(c->stream, c->rho_cur, c->np, c->X, c->n));
+      HIPCHK(c, hipMemcpyAsync(rho, c->X, sizeof(double) * 2 * n2, hipMemcpyDeviceToHost,
+                               c->stream));
+    }
+    if (rho_prev) {
+      REQUIRE(c, c->has_prev, TD_ESTATE, "no previous density matrix (next step is Euler)");
+      HIPCHK(c, td::wide_to_interleaved(c->stream, c->rho_prev, c->np, c->X, c->n));
+      HIPCHK(c, hipMemcpyAsync(rho_prev, c->X, sizeof(double) * 2 * n2, hipMemcpyDeviceToHost,
+                               c->stream));
+    }
+    sync(c);
+    if (step) *step = c->step;
+    if (has_prev) *has_prev = c->has_prev ? 1 : 0;
+  });
+}
+
+td_status td_set_rho(td_ctx* ctx, const double* rho, const double* rho_prev, int64_t step) {
+  return guarded(ctx, [&] {
+    td_ctx* c = ctx;
+    REQUIRE(c, rho, TD_EINVAL, "rho must not be null");
+    const size_t n2 = (size_t)c->n * c->n;
+    REQUIRE(c, finite_all(rho, 2 * n2) && (!rho_prev || finite_all(rho_prev, 2 * n2)),
+            TD_EINVAL, "non-finite density matrix");
+    HIPCHK(c, hipMemcpyAsync(c->X, rho, sizeof(double) * 2 * n2, hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, td::interleaved_to_wide(c->stream, c->X, c->n, c->rho_cur, c->np));
+    if (rho_prev) {
+      HIPCHK(c, hipMemcpyAsync(c->X, rho_prev, sizeof(double) * 2 * n2, hipMemcpyHostToDevice,
+                               c->stream));
+      HIPCHK(c, td::interleaved_to_wide(c->stream, c->X, c->n, c->rho_prev, c->np));
+    }
+    c->has_prev = rho_prev != nullptr;
+    c->step = step;
+    sync(c);
+    refresh(c);
+  });
+}
+
+td_status td_get_info(td_ctx* ctx, td_info* info) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx, info, TD_EINVAL, "null output");
+    ctx->info.step = ctx->step;
+    ctx->info.has_prev = ctx->has_prev ? 1 : 0;
+    *info = ctx->info;
+  });
+}
+
+td_status td_get_kernel_time(td_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx, kind >= 0 && kind < TD_KT_COUNT && total_ms && launches, TD_EINVAL,
+            "invalid kernel class or output");
+    *total_ms = ctx->kt_ms[kind];
+    *launches = ctx->kt_n[kind];
+  });
+}
+
+td_status td_reset_kernel_time(td_ctx* ctx) {
+  return guarded(ctx, [&] {
+    for (int q = 0; q < TD_KT_COUNT; ++q) {
+      ctx->kt_ms[q] = 0.0;
+      ctx->kt_n[q] = 0;
+    }
+  });
+}
+
+td_status td_get_forces(td_ctx* ctx, double* forces) {
+  (void)forces;
+  if (!ctx) return TD_EINVAL;
+  ctx->err = "forces need moving nuclei (Ehrenfest dynamics), which this build does not run";
+  return TD_ENOTSUP;
+}
+
+const char* td_last_error(const td_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+const char* td_status_string(int32_t s) {
+  switch (s) {
+    case TD_OK: return "TD_OK";
+    case TD_EINVAL: return "TD_EINVAL";
+    case TD_ENOMEM: return "TD_ENOMEM";
+    case TD_EHIP: return "TD_EHIP";
+    case TD_ENOTPOSDEF: return "TD_ENOTPOSDEF";
+    case TD_ESCF: return "TD_ESCF";
+    case TD_EUNSTABLE: return "TD_EUNSTABLE";
+    case TD_ENOTSUP: return "TD_ENOTSUP";
+    case TD_ESTATE: return "TD_ESTATE";
+    default: return "unknown status";
+  }
+}
+
+void td_destroy(td_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  free_all(ctx);
+  delete ctx;
+}
+
+td_status td_util_gemm(int32_t precision, int32_t n_slices, int32_t m, int32_t n, int32_t k,
+                       const double* A, const double* B, double* C, char* err, int32_t errlen) {
+  td_ctx tmp;
+  td_ctx* c = &tmp;
+  td_status st = guarded(c, [&] {
+    REQUIRE(c, A && B && C && m > 0 && n > 0 && k > 0, TD_EINVAL, "invalid gemm arguments");
+    REQUIRE(c, precision == TD_FP64, TD_ENOTSUP, "only FP64 products are available");
+    (void)n_slices;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    REQUIRE(c, e == hipSuccess && ndev > 0, TD_EHIP, "no HIP device available");
+    HIPCHK(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+    const int mp = round_up(m, td::kGemmTile), npd = round_up(n, td::kGemmTile),
+              kp = round_up(k, td::kGemmTile);
+    dalloc(c, &c->S, (size_t)mp * kp);
+    dalloc(c, &c->H, (size_t)kp * npd);
+    dalloc(c, &c->A, (size_t)mp * npd);
+    HIPCHK(c, hipMemcpy2DAsync(c->S, sizeof(double) * kp, A, sizeof(double) * k,
+                               sizeof(double) * k, m, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpy2DAsync(c->H, sizeof(double) * npd, B, sizeof(double) * n,
+                               sizeof(double) * n, k, hipMemcpyHostToDevice, c->stream));
+    gemm(c, 0, mp, npd, kp, 1.0, c->S, kp, c->H, npd, c->A, npd);
+    HIPCHK(c, hipMemcpy2DAsync(C, sizeof(double) * n, c->A, sizeof(double) * npd,
+                               sizeof(double) * n, m, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+  });
+  set_err(err, errlen, st == TD_OK ? "" : c->err);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  free_all(c);
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,327 @@
+"""ctypes binding of libtddftb.so: the C ABI of tddftb.h, one Python name per entry point.
+
+Argument marshalling only: numpy arrays are passed as host pointers and
+every step of the propagation runs in the library's HIP kernels. There is
+no fallback: if the library is not built or cannot be loaded, importing
+this module's functions raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libtddftb.so")
+
+TD_OK, TD_EINVAL, TD_ENOMEM, TD_EHIP, TD_ENOTPOSDEF = 0, -1, -2, -3, -4
+TD_ESCF, TD_EUNSTABLE, TD_ENOTSUP, TD_ESTATE = -5, -6, -7, -8
+TD_FP64, TD_SPLIT_BF16 = 0, 1
+TD_KT_GEMM_SH, TD_KT_GEMM_ARHO, TD_KT_UPDATE, TD_KT_OTHER = 0, 1, 2, 3
+
+EXPORTED = [
+    "td_default_options", "td_create", "td_kick", "td_step", "td_get_charges",
+    "td_get_dipole", "td_get_dipole_series", "td_get_energy", "td_get_rho", "td_set_rho",
+    "td_get_info", "td_get_kernel_time", "td_reset_kernel_time", "td_get_forces",
+    "td_last_error", "td_status_string", "td_destroy", "td_util_gemm",
+]
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+class TdSystem(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int32), ("n_orb", ctypes.c_int32),
+                ("orb_offset", _ip), ("positions", _dp), ("S", _dp), ("H0", _dp),
+                ("gamma", _dp), ("q0", _dp), ("n_elec", ctypes.c_int32), ("rho0", _dp)]
+
+
+class TdOptions(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("n_slices", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("scc_tol", ctypes.c_double),
+                ("scc_maxiter", ctypes.c_int32), ("mix_beta", ctypes.c_double),
+                ("mix_history", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("hip_stream", ctypes.c_void_p)]
+
+
+class TdInfo(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int32), ("n_orb", ctypes.c_int32), ("n_pad", ctypes.c_int32),
+                ("inverse_iterations", ctypes.c_int32), ("inverse_residual", ctypes.c_double),
+                ("scc_iterations", ctypes.c_int32), ("scc_residual", ctypes.c_double),
+                ("purification_iterations", ctypes.c_int32),
+                ("purification_error", ctypes.c_double),
+                ("spectrum_lo", ctypes.c_double), ("spectrum_hi", ctypes.c_double),
+                ("step", ctypes.c_int64), ("has_prev", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_string(status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the library (once). Raises if it is missing: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    sig = {
+        "td_default_options": (None, [ctypes.POINTER(TdOptions)]),
+        "td_create": (ctypes.c_int32, [ctypes.POINTER(TdSystem), ctypes.POINTER(TdOptions),
+                                       ctypes.POINTER(vp), ctypes.c_char_p, ctypes.c_int32]),
+        "td_kick": (ctypes.c_int32, [vp, ctypes.c_double, _dp]),
+        "td_step": (ctypes.c_int32, [vp, ctypes.c_int32, _dp]),
+        "td_get_charges": (ctypes.c_int32, [vp, _dp]),
+        "td_get_dipole": (ctypes.c_int32, [vp, _dp]),
+        "td_get_dipole_series": (ctypes.c_int32, [vp, _dp, ctypes.c_int32, _ip]),
+        "td_get_energy": (ctypes.c_int32, [vp, _dp, _dp]),
+        "td_get_rho": (ctypes.c_int32, [vp, _dp, _dp, ctypes.POINTER(ctypes.c_int64), _ip]),
+        "td_set_rho": (ctypes.c_int32, [vp, _dp, _dp, ctypes.c_int64]),
+        "td_get_info": (ctypes.c_int32, [vp, ctypes.POINTER(TdInfo)]),
+        "td_get_kernel_time": (ctypes.c_int32, [vp, ctypes.c_int32, _dp,
+                                                ctypes.POINTER(ctypes.c_int64)]),
+        "td_reset_kernel_time": (ctypes.c_int32, [vp]),
+        "td_get_forces": (ctypes.c_int32, [vp, _dp]),
+        "td_last_error": (ctypes.c_char_p, [vp]),
+        "td_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+        "td_destroy": (None, [vp]),
+        "td_util_gemm": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp,
+                                          ctypes.c_char_p, ctypes.c_int32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray], dtype=np.float64):
+    if a is None:
+        return None
+    assert a.dtype == dtype and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_ip if dtype == np.int32 else _dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def status_string(status: int) -> str:
+    return load().td_status_string(status).decode()
+
+
+def td_default_options() -> TdOptions:
+    o = TdOptions()
+    load().td_default_options(ctypes.byref(o))
+    return o
+
+
+class _Keep:
+    """Host arrays kept alive while a td_system refers to them."""
+
+
+def td_create(system, options: Optional[TdOptions] = None, rho0: Optional[np.ndarray] = None):
+    """td_create: returns an opaque context handle (c_void_p)."""
+    lib = load()
+    keep = _Keep()
+    keep.off = np.ascontiguousarray(system.orb_offset, dtype=np.int32)
+    keep.pos = _f64(system.positions)
+    keep.S = _f64(system.S)
+    keep.H0 = _f64(system.H0)
+    keep.gamma = _f64(system.gamma)
+    keep.q0 = _f64(system.q0)
+    keep.rho0 = None if rho0 is None else np.ascontiguousarray(rho0, dtype=np.complex128)
+    s = TdSystem(n_atoms=len(keep.q0), n_orb=int(keep.off[-1]), orb_offset=_ptr(keep.off, np.int32),
+                 positions=_ptr(keep.pos), S=_ptr(keep.S), H0=_ptr(keep.H0),
+                 gamma=_ptr(keep.gamma), q0=_ptr(keep.q0), n_elec=int(system.n_elec),
+                 rho0=None if keep.rho0 is None else keep.rho0.ctypes.data_as(_dp))
+    opt = options if options is not None else td_default_options()
+    ctx = ctypes.c_void_p()
+    err = ctypes.create_string_buffer(1024)
+    st = lib.td_create(ctypes.byref(s), ctypes.byref(opt), ctypes.byref(ctx), err, 1024)
+    if st != TD_OK:
+        raise TdError(st, err.value.decode())
+    return ctx
+
+
+def _check(ctx, st):
+    if st != TD_OK:
+        raise TdError(st, load().td_last_error(ctx).decode())
+
+
+def td_kick(ctx, e0: float, direction) -> None:
+    d = _f64(direction)
+    _check(ctx, load().td_kick(ctx, float(e0), _ptr(d)))
+
+
+def td_step(ctx, n: int, field: Optional[np.ndarray] = None) -> None:
+    f = None if field is None else _f64(field).reshape(-1)
+    if f is not None and f.size != 3 * n:
+        raise ValueError("field must have shape [n, 3]")
+    _check(ctx, load().td_step(ctx, int(n), _ptr(f)))
+
+
+def td_get_charges(ctx, n_atoms: int) -> np.ndarray:
+    out = np.empty(n_atoms)
+    _check(ctx, load().td_get_charges(ctx, _ptr(out)))
+    return out
+
+
+def td_get_dipole(ctx) -> np.ndarray:
+    out = np.empty(3)
+    _check(ctx, load().td_get_dipole(ctx, _ptr(out)))
+    return out
+
+
+def td_get_dipole_series(ctx, cap: int) -> np.ndarray:
+    out = np.empty((max(cap, 1), 3))
+    n = ctypes.c_int32()
+    _check(ctx, load().td_get_dipole_series(ctx, _ptr(out), int(cap), ctypes.byref(n)))
+    return out[:min(cap, n.value)]
+
+
+def td_get_energy(ctx, field=None) -> float:
+    f = None if field is None else _f64(field)
+    e = np.empty(1)
+    _check(ctx, load().td_get_energy(ctx, _ptr(f), _ptr(e)))
+    return float(e[0])
+
+
+def td_get_rho(ctx, n_orb: int, with_prev: bool = False):
+    rho = np.empty((n_orb, n_orb), dtype=np.complex128)
+    prev = np.empty((n_orb, n_orb), dtype=np.complex128) if with_prev else None
+    step = ctypes.c_int64()
+    has_prev = ctypes.c_int32()
+    _check(ctx, load().td_get_rho(ctx, rho.ctypes.data_as(_dp),
+                                  None if prev is None else prev.ctypes.data_as(_dp),
+                                  ctypes.byref(step), ctypes.byref(has_prev)))
+    return rho, prev, step.value, bool(has_prev.value)
+
+
+def td_set_rho(ctx, rho: np.ndarray, rho_prev: Optional[np.ndarray], step: int) -> None:
+    r = np.ascontiguousarray(rho, dtype=np.complex128)
+    p = None if rho_prev is None else np.ascontiguousarray(rho_prev, dtype=np.complex128)
+    _check(ctx, load().td_set_rho(ctx, r.ctypes.data_as(_dp),
+                                  None if p is None else p.ctypes.data_as(_dp), int(step)))
+
+
+def td_get_info(ctx) -> dict:
+    info = TdInfo()
+    _check(ctx, load().td_get_info(ctx, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def td_get_kernel_time(ctx, kind: int):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(ctx, load().td_get_kernel_time(ctx, int(kind), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def td_reset_kernel_time(ctx) -> None:
+    _check(ctx, load().td_reset_kernel_time(ctx))
+
+
+def td_get_forces(ctx, n_atoms: int) -> np.ndarray:
+    out = np.empty((n_atoms, 3))
+    _check(ctx, load().td_get_forces(ctx, _ptr(out)))
+    return out
+
+
+def td_last_error(ctx) -> str:
+    return load().td_last_error(ctx).decode()
+
+
+def td_destroy(ctx) -> None:
+    if ctx:
+        load().td_destroy(ctx)
+
+
+def td_util_gemm(A: np.ndarray, B: np.ndarray, precision: int = TD_FP64,
+                 n_slices: int = 4) -> np.ndarray:
+    A = _f64(A)
+    B = _f64(B)
+    m, k = A.shape
+    k2, n = B.shape
+    assert k == k2
+    C = np.empty((m, n))
+    err = ctypes.create_string_buffer(1024)
+    st = load().td_util_gemm(int(precision), int(n_slices), m, n, k, _ptr(A), _ptr(B), _ptr(C),
+                             err, 1024)
+    if st != TD_OK:
+        raise TdError(st, err.value.decode())
+    return C
+
+
+class Propagator:
+    """Convenience wrapper owning one context (one trajectory)."""
+
+    def __init__(self, system, dt=0.2, precision=TD_FP64, n_slices=4, rho0=None, profile=False,
+                 scc_tol=1e-12, scc_maxiter=300):
+        opt = td_default_options()
+        opt.dt = dt
+        opt.precision = precision
+        opt.n_slices = n_slices
+        opt.profile = 1 if profile else 0
+        opt.scc_tol = scc_tol
+        opt.scc_maxiter = scc_maxiter
+        self.n_atoms = len(system.q0)
+        self.n_orb = int(system.orb_offset[-1])
+        self.ctx = td_create(system, opt, rho0=rho0)
+
+    def kick(self, e0, direction):
+        td_kick(self.ctx, e0, direction)
+
+    def step(self, n, field=None):
+        td_step(self.ctx, n, field)
+        return td_get_dipole_series(self.ctx, n)
+
+    def dipole(self):
+        return td_get_dipole(self.ctx)
+
+    def charges(self):
+        return td_get_charges(self.ctx, self.n_atoms)
+
+    def energy(self, field=None):
+        return td_get_energy(self.ctx, field)
+
+    def rho(self, with_prev=False):
+        return td_get_rho(self.ctx, self.n_orb, with_prev)
+
+    def set_rho(self, rho, rho_prev=None, step=0):
+        td_set_rho(self.ctx, rho, rho_prev, step)
+
+    def info(self):
+        return td_get_info(self.ctx)
+
+    def kernel_time(self, kind):
+        return td_get_kernel_time(self.ctx, kind)
+
+    def reset_kernel_time(self):
+        td_reset_kernel_time(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            td_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

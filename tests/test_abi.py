@@ -1,0 +1,91 @@
+"""The C ABI library loads and exports every declared entry point (CPU only)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tddftb.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"TD_API\s+[\w\s\*]+?\b(td_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_1912_03174_amd import tddftb as T
+    if not os.path.exists(T.LIB_PATH):
+        pytest.fail("libtddftb.so is not built (run __graft_entry__.build())")
+    T.load()
+    return T
+
+
+def test_every_declared_symbol_is_exported(T):
+    names = declared()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(T.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", T.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r" T (td_\w+)", out))
+    assert set(names) == exported
+    assert set(T.EXPORTED) == set(names)
+
+
+def test_defaults_and_status_strings(T):
+    o = T.td_default_options()
+    assert o.precision == T.TD_FP64 and o.dt == 0.2 and o.n_slices == 4
+    assert T.status_string(T.TD_EINVAL) == "TD_EINVAL"
+    assert T.status_string(-99) == "unknown status"
+
+
+def test_invalid_arguments_rejected_before_device(T):
+    s = W.flake_c24h16()
+    bad = W.flake_c24h16()
+    bad.n_elec = 3
+    with pytest.raises(T.TdError) as e:
+        T.td_create(bad)
+    assert e.value.status == T.TD_EINVAL
+    bad = W.flake_c24h16()
+    bad.orb_offset = bad.orb_offset.copy()
+    bad.orb_offset[3] = bad.orb_offset[2]
+    with pytest.raises(T.TdError) as e:
+        T.td_create(bad)
+    assert e.value.status == T.TD_EINVAL
+    bad = W.flake_c24h16()
+    bad.S = bad.S.copy()
+    bad.S[0, 1] += 1e-6
+    with pytest.raises(T.TdError) as e:
+        T.td_create(bad)
+    assert e.value.status == T.TD_EINVAL
+    o = T.td_default_options()
+    o.dt = -0.1
+    with pytest.raises(T.TdError) as e:
+        T.td_create(s, o)
+    assert e.value.status == T.TD_EINVAL
+    lib = T.load()
+    assert lib.td_kick(None, 1e-3, None) == T.TD_EINVAL
+    assert lib.td_step(None, 1, None) == T.TD_EINVAL
+
+
+def test_no_device_is_an_error_not_a_fallback(T):
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except Exception:
+        pass
+    with pytest.raises(T.TdError) as e:
+        T.td_create(W.flake_c24h16())
+    assert e.value.status == T.TD_EHIP
+    with pytest.raises(T.TdError) as e:
+        T.td_util_gemm(np.eye(4), np.eye(4))
+    assert e.value.status == T.TD_EHIP

@@ -1,0 +1,303 @@
+"""GPU path (through the C ABI) against the CPU oracle, element by element.
+
+Tolerances: FP64 path, dipole relative error <= 1e-10 over the run
+(max_k |mu_gpu(t_k) - mu_ref(t_k)| / max_k |mu_ref(t_k) - mu_ref(0)|);
+density matrices within 1e-12 absolute (entries are O(1)).
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DIPOLE_TOL = 1e-10
+
+
+def _T():
+    from paper_1912_03174_amd import tddftb as T
+    return T
+
+
+def dipole_rel_err(test, ref):
+    ref = np.asarray(ref)
+    scale = np.abs(ref - ref[0]).max()
+    return np.abs(np.asarray(test) - ref).max() / scale
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def flake():
+    s = W.flake_c24h16()
+    gs = O.ground_state(s, tol=1e-13)
+    Sinv = O.inverse_overlap(s.S)
+    return s, gs, Sinv
+
+
+# ---------------------------------------------------------------- products
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (17, 45, 33), (128, 128, 128), (300, 257, 129),
+                                   (384, 640, 512), (1024, 256, 2048)])
+def test_gemm_fp64(m, n, k):
+    T = _T()
+    say(f"gemm {m}x{n}x{k}")
+    A = W.random_matrix(m, k, seed=m * 7 + k)
+    B = W.random_matrix(k, n, seed=n * 11 + k)
+    C = T.td_util_gemm(A, B)
+    ref = A @ B
+    bound = 1e-15 * k * np.abs(A).max() * np.abs(B).max()
+    assert np.abs(C - ref).max() <= 4 * bound + 1e-300
+
+
+# ---------------------------------------------------------------- ground state and kick
+
+def test_ground_state_matches_oracle(flake):
+    T = _T()
+    s, gs, _ = flake
+    say("ground state flake")
+    p = T.Propagator(s, scc_tol=1e-13)
+    info = p.info()
+    assert info["scc_residual"] < 1e-13
+    assert info["inverse_residual"] < 1e-12
+    rho, _, step, has_prev = p.rho()
+    assert step == 0 and not has_prev
+    assert np.abs(rho.imag).max() == 0.0
+    assert np.abs(rho.real - gs.rho).max() < 1e-11
+    assert np.abs(p.charges() - gs.dq).max() < 1e-11
+    mu0 = O.dipole(gs.dq, s.positions)
+    assert np.abs(p.dipole() - mu0).max() < 1e-10
+    e_ref = O.energy(gs.rho, s.H0, s.gamma, gs.dq, s.positions)
+    assert abs(p.energy() - e_ref) < 1e-10 * abs(e_ref)
+    p.close()
+
+
+def test_kick_matches_oracle(flake):
+    T = _T()
+    s, gs, Sinv = flake
+    say("kick flake")
+    p = T.Propagator(s, rho0=gs.rho.astype(np.complex128))
+    p.kick(1e-3, (1.0, 0.5, 0.0))
+    rk = O.kick(gs.rho, s.S, Sinv, s.positions, s.orb_offset, 1e-3, (1.0, 0.5, 0.0))
+    rho, _, _, has_prev = p.rho()
+    assert not has_prev
+    assert np.abs(rho - rk).max() < 1e-13
+    assert np.abs(rho - rho.conj().T).max() == 0.0
+    p.close()
+
+
+# ---------------------------------------------------------------- propagation parity
+
+def test_flake_500_steps_from_same_kicked_state(flake):
+    """Propagation alone: both sides start from the oracle's kicked density."""
+    T = _T()
+    s, gs, Sinv = flake
+    say("flake 500 steps injected")
+    rk = O.kick(gs.rho, s.S, Sinv, s.positions, s.orb_offset, 1e-3, (1.0, 0.0, 0.0))
+    ref = O.propagate(s, rk, 500, 0.2, Sinv=Sinv, record_energy=False)
+    p = T.Propagator(s, rho0=rk)
+    mu = p.step(500)
+    assert mu.shape == (500, 3)
+    assert dipole_rel_err(mu, ref.dipoles) < DIPOLE_TOL
+    rho, prev, step, has_prev = p.rho(with_prev=True)
+    assert step == 500 and has_prev
+    assert np.abs(rho - ref.rho).max() < 1e-11
+    assert np.abs(prev - ref.rho_prev).max() < 1e-11
+    assert np.abs(p.charges() - O.charge_fluctuations(ref.rho, s.S, s.orb_offset, s.q0)).max() < 1e-11
+    p.close()
+
+
+def test_flake_end_to_end_own_ground_state(flake):
+    """GPU ground state + GPU kick + 500 steps against the oracle's whole chain."""
+    T = _T()
+    s, gs, Sinv = flake
+    say("flake end to end")
+    rk = O.kick(gs.rho, s.S, Sinv, s.positions, s.orb_offset, 1e-3, (1.0, 0.0, 0.0))
+    ref = O.propagate(s, rk, 500, 0.2, Sinv=Sinv, record_energy=False)
+    p = T.Propagator(s, scc_tol=1e-13)
+    p.kick(1e-3, (1.0, 0.0, 0.0))
+    mu = p.step(500)
+    assert dipole_rel_err(mu, ref.dipoles) < DIPOLE_TOL
+    p.close()
+
+
+def test_flake_driven_by_laser_with_energy(flake):
+    T = _T()
+    s, gs, Sinv = flake
+    say("flake laser 300 steps")
+    n = 300
+    field = W.sin2_pulse(np.arange(n + 1) * 0.2, 0.005, 0.1, n * 0.2, (0.3, 1.0, 0.0))
+    ref = O.propagate(s, gs.rho, n, 0.2, Sinv=Sinv, field=field[:n])
+    p = T.Propagator(s, rho0=gs.rho)
+    mu = p.step(n, field[:n])
+    assert dipole_rel_err(mu, ref.dipoles) < DIPOLE_TOL
+    dq_ref = O.charge_fluctuations(ref.rho, s.S, s.orb_offset, s.q0)
+    assert np.abs(p.charges() - dq_ref).max() < 1e-11
+    e_ref = O.energy(ref.rho, s.H0, s.gamma, dq_ref, s.positions, field[n])
+    assert abs(p.energy(field[n]) - e_ref) < 1e-10 * abs(e_ref)
+    p.close()
+
+
+@pytest.mark.parametrize("which", ["dimer", "benzene", "strip314", "strip686"])
+def test_ragged_sizes(which):
+    """Sizes from one orbital pair to several 128-tiles plus a ragged tail."""
+    T = _T()
+    s = {"dimer": lambda: W.dimer(u=1.0),
+         "benzene": lambda: W.benzene(),
+         "strip314": lambda: W.small_strip(8, 4, seed=1),
+         "strip686": lambda: W.small_strip(20, 10, seed=1)}[which]()
+    say(f"ragged {which} n_orb={s.n_orb}")
+    gs = O.ground_state(s, tol=1e-13)
+    Sinv = O.inverse_overlap(s.S)
+    rk = O.kick(gs.rho, s.S, Sinv, s.positions, s.orb_offset, 1e-3, (1.0, 1.0, 0.0))
+    ref = O.propagate(s, rk, 200, 0.2, Sinv=Sinv, record_energy=False)
+    p = T.Propagator(s, rho0=rk)
+    mu = p.step(200)
+    assert dipole_rel_err(mu, ref.dipoles) < DIPOLE_TOL
+    assert np.abs(p.rho()[0] - ref.rho).max() < 1e-11
+    # the GPU's own ground state
+    q = T.Propagator(s, scc_tol=1e-13)
+    assert np.abs(q.rho()[0].real - gs.rho).max() < 1e-10
+    p.close()
+    q.close()
+
+
+# ---------------------------------------------------------------- state handling
+
+def test_checkpoint_restore_is_bitwise(flake):
+    T = _T()
+    s, gs, _ = flake
+    say("checkpoint")
+    field = W.sin2_pulse(np.arange(100) * 0.2, 0.004, 0.2, 20.0, (1.0, 0.0, 0.0))
+    a = T.Propagator(s, rho0=gs.rho)
+    a.kick(1e-3, (0.0, 1.0, 0.0))
+    a.step(50, field[:50])
+    rho, prev, step, _ = a.rho(with_prev=True)
+    mu_a = a.step(50, field[50:])
+    b = T.Propagator(s, rho0=gs.rho)
+    b.set_rho(rho, prev, step)
+    mu_b = b.step(50, field[50:])
+    assert np.array_equal(mu_a, mu_b)
+    assert np.array_equal(a.rho()[0], b.rho()[0])
+    assert b.info()["step"] == 100
+    a.close()
+    b.close()
+
+
+def test_repeat_runs_are_bitwise_identical(flake):
+    T = _T()
+    s, gs, _ = flake
+    say("repeat")
+    out = []
+    for _ in range(2):
+        p = T.Propagator(s, scc_tol=1e-13)
+        p.kick(1e-3, (1.0, 0.0, 0.0))
+        out.append(p.step(100))
+        p.close()
+    assert np.array_equal(out[0], out[1])
+
+
+def test_electron_count_and_hermiticity_on_gpu(flake):
+    T = _T()
+    s, gs, Sinv = flake
+    say("invariants")
+    p = T.Propagator(s, rho0=gs.rho)
+    p.kick(1e-2, (1.0, 1.0, 1.0))
+    p.step(400)
+    rho = p.rho()[0]
+    assert np.abs(rho - rho.conj().T).max() == 0.0
+    assert abs(np.real(np.trace(rho @ s.S)) - s.n_elec) < 1e-11
+    p.close()
+
+
+def test_errors_are_reported(flake):
+    T = _T()
+    s, gs, _ = flake
+    say("errors")
+    bad = dataclasses.replace(s, S=-s.S)
+    with pytest.raises(T.TdError) as e:
+        T.Propagator(bad)
+    assert e.value.status == T.TD_ENOTPOSDEF
+    p = T.Propagator(s, rho0=gs.rho)
+    with pytest.raises(T.TdError) as e:
+        T.td_get_forces(p.ctx, s.n_atoms)
+    assert e.value.status == T.TD_ENOTSUP
+    with pytest.raises(T.TdError) as e:
+        p.rho(with_prev=True)
+    assert e.value.status == T.TD_ESTATE
+    nan = gs.rho.astype(np.complex128)
+    nan[0, 0] = np.nan
+    with pytest.raises(T.TdError) as e:
+        p.set_rho(nan)
+    assert e.value.status == T.TD_EINVAL
+    # an unstable time step is reported, not silently propagated
+    q = T.Propagator(s, rho0=gs.rho, dt=2.0)
+    q.kick(1e-3, (1.0, 0.0, 0.0))
+    with pytest.raises(T.TdError) as e:
+        q.step(3000)
+    assert e.value.status == T.TD_EUNSTABLE
+    p.close()
+    q.close()
+
+
+# ---------------------------------------------------------------- full size
+
+@pytest.fixture(scope="module")
+def strip4096():
+    return W.workload(3)
+
+
+def test_full_size_one_step_sampled_rows(strip4096):
+    """N_orb = 4096 in the benchmark's launch configuration: rows of one leapfrog step."""
+    T = _T()
+    w = strip4096
+    s = w.system
+    n = s.n_orb
+    say("full size 4096 sampled rows")
+    # seeded Hermitian densities around a scaled identity (inputs, not physics)
+    r1, i1 = W.random_hermitian_pair(n, seed=41, scale=1e-3, base=0.5 * np.eye(n))
+    r0, i0 = W.random_hermitian_pair(n, seed=42, scale=1e-3, base=0.5 * np.eye(n))
+    cur, prev = r1 + 1j * i1, r0 + 1j * i0
+    E = np.array([[0.0, 0.004, 0.0]])
+    p = T.Propagator(s, rho0=cur)
+    p.set_rho(cur, prev, 10)
+    p.step(1, E)
+    new = p.rho()[0]
+    Sinv = O.inverse_overlap(s.S)
+    dq = O.charge_fluctuations(cur, s.S, s.orb_offset, s.q0)
+    V = O.external_potential(s.positions, E[0])
+    H = O.scc_hamiltonian_fast(s.H0, s.S, s.gamma, dq, s.orb_offset, V)
+    rows = np.random.default_rng(0).choice(n, size=24, replace=False)
+    ref = O.leapfrog_step(prev[rows], O.rho_dot_rows(cur, H, Sinv, rows), w.dt)
+    assert np.abs(new[rows] - ref).max() < 1e-12
+    assert np.abs(new - new.conj().T).max() == 0.0
+    mu_ref = O.dipole(dq, s.positions)
+    mu = T.td_get_dipole_series(p.ctx, 1)[0]
+    assert np.abs(mu - mu_ref).max() < 1e-9 * np.abs(mu_ref).max()
+    p.close()
+
+
+def test_full_size_ground_state_properties(strip4096):
+    """GPU SCC ground state at N_orb = 4096: idempotent, N_e, self-consistent, stationary."""
+    T = _T()
+    s = strip4096.system
+    say("full size 4096 ground state")
+    p = T.Propagator(s, scc_tol=1e-11)
+    info = p.info()
+    say(f"info {info}")
+    rho = p.rho()[0].real
+    assert abs(np.trace(rho @ s.S) - s.n_elec) < 1e-8
+    rs = rho @ s.S
+    assert np.abs(rs @ rho - 2.0 * rho).max() < 1e-9
+    dq = O.charge_fluctuations(rho, s.S, s.orb_offset, s.q0)
+    assert np.abs(p.charges() - dq).max() < 1e-10
+    mu = p.step(5)
+    assert np.abs(mu - mu[0]).max() < 1e-8
+    p.close()

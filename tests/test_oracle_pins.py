@@ -365,3 +365,14 @@ def test_dimer_spectrum_peak_and_sign():
     assert abs(omegas[k] - w0) < 0.01 * w0
     # static limit: alpha(w -> small) approaches the positive static polarisability
     assert np.real(alpha[0]) > 0
+
+
+def test_row_sampled_rhodot_equals_full(flake, flake_gs):
+    """Row-restricted Eq. 10 equals the rows of the full (pinned) derivative."""
+    s = flake
+    Sinv = O.inverse_overlap(s.S)
+    rk = O.kick(flake_gs.rho, s.S, Sinv, s.positions, s.orb_offset, 1e-2, (1.0, 1.0, 0.0))
+    H = O.scc_hamiltonian_fast(s.H0, s.S, s.gamma, flake_gs.dq, s.orb_offset)
+    rows = [0, 7, 50, s.n_orb - 1]
+    full = O.rho_dot(rk, H, Sinv)
+    assert np.abs(O.rho_dot_rows(rk, H, Sinv, rows) - full[rows]).max() < 1e-14
