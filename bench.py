@@ -56,7 +56,7 @@ def cpu_baseline(w, n_steps):
         threads = os.cpu_count()
     s = w.system
     Sinv = O.inverse_overlap(s.S)
-    r, i = W.random_hermitian_pair(s.n_orb, seed=5, scale=1e-3, base=0.5 * np.eye(s.n_orb))
+    r, i = W.random_hermitian_pair(s.n_orb, seed=5, scale=1e-3, base=np.eye(s.n_orb))
     t0 = time.perf_counter()
     O.propagate(s, r + 1j * i, n_steps, w.dt, Sinv=Sinv, field=w.field(0, n_steps),
                 record_energy=False)

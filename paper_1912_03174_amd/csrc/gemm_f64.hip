@@ -125,8 +125,8 @@ __global__ __launch_bounds__(256) void dgemm_nn(const double* __restrict__ A, in
     __syncthreads();
   }
 
-  // Accumulator layout of the 16x16 f64 block: lane holds rows 4*(lane/16)+r,
-  // column lane%16, r = 0..3.
+  // Accumulator layout of the 16x16 f64 block: register r of lane l holds
+  // row l/16 + 4 r, column l%16.
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void dgemm_nn(const double* __restrict__ A, in
       const int col = n0 + wn * 64 + j * 16 + l16;
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
-        const int row = m0 + wm * 64 + i * 16 + lk * 4 + rr;
+        const int row = m0 + wm * 64 + i * 16 + lk + 4 * rr;
         double v = alpha * acc[i][j][rr];
         if (beta != 0.0) v += beta * Cin[(size_t)row * ldcin + col];
         C[(size_t)row * ldc + col] = v;

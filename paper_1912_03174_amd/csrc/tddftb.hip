@@ -253,7 +253,15 @@ void ground_state(td_ctx* c) {
   }
   c->info.scc_iterations = std::min(it, c->opt.scc_maxiter);
   c->info.scc_residual = res;
-  REQUIRE(c, res < c->opt.scc_tol, TD_ESCF, "SCC ground state did not converge");
+  if (!(res < c->opt.scc_tol)) {
+    char msg[256];
+    std::snprintf(msg, sizeof msg,
+                  "SCC ground state did not converge: %d cycles, max |dq_out - dq_in| = %.3e, "
+                  "last purification %d iterations",
+                  c->info.scc_iterations, res, c->info.purification_iterations);
+    c->err = msg;
+    throw Fail{TD_ESCF};
+  }
 }
 
 void ensure_events(td_ctx* c, size_t count) {

@@ -130,10 +130,16 @@ def saturate(pts, bonds, n_pairs, rng):
     """Hydrogen positions (Angstrom) for a planar carbon skeleton.
 
     Each carbon with two C neighbours gets one H along its open sigma
-    direction, except for ``n_pairs`` seeded disjoint pairs of *bonded*
-    edge carbons: each carbon of such a pair gets two H, above and below
-    the plane at the tetrahedral angle (a hydrogenated edge C=C bond,
-    which keeps the pi system closed-shell).
+    direction, except for sp3 CH2 sites, whose carbon gets two H above and
+    below the plane at the tetrahedral angle:
+
+    * every isolated edge carbon (two C neighbours, neither of them an
+      edge carbon: a zigzag site) is a CH2 site, which removes the
+      zigzag end states that would otherwise sit at the Fermi level of a
+      finite armchair strip;
+    * ``n_pairs`` seeded disjoint pairs of *bonded* edge carbons are CH2
+      sites (a hydrogenated edge C=C bond, keeping the pi system
+      closed-shell).
     """
     deg = bonds.sum(1)
     if (deg < 2).any():
@@ -141,7 +147,9 @@ def saturate(pts, bonds, n_pairs, rng):
     n = len(pts)
     pairs = [(i, j) for i in range(n) for j in range(i + 1, n)
              if bonds[i, j] and deg[i] == 2 and deg[j] == 2]
-    used, chosen = set(), 0
+    in_pair = {x for p in pairs for x in p}
+    used = {i for i in range(n) if deg[i] == 2 and i not in in_pair}
+    chosen = 0
     if n_pairs:
         for k in rng.permutation(len(pairs)):
             i, j = pairs[k]
@@ -282,9 +290,9 @@ def strip_c640h384(seed=1002) -> System:
 
 
 def strip_c938h344(seed=1003) -> System:
-    """7-line armchair strip, 133 columns, 35 hydrogenated edge pairs: N_orb = 4096."""
+    """7-line armchair strip, 133 columns, 2 zigzag + 34 pair CH2 sites: N_orb = 4096."""
     pts, bonds = armchair_skeleton(3, 133)
-    sp, pos = molecule(pts, bonds, n_pairs=35, seed=seed)
+    sp, pos = molecule(pts, bonds, n_pairs=34, seed=seed)
     return make_system(sp, pos, seed, name="C938H344 strip")
 
 
