@@ -27,6 +27,9 @@ def command(out: str = LIB) -> list:
             "-Wall", "-Wno-unused-function",
             # no packed-FP32 instructions in device code
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # matrix-core accumulators in ordinary VGPRs: avoids AGPR<->VGPR
+            # copies of the accumulators around the K loop (gfx950 allows both)
+            "-mllvm", "-amdgpu-mfma-vgpr-form",
             "-I", INCLUDE, *[os.path.join(CSRC, s) for s in SOURCES], "-o", out]
 
 

@@ -72,33 +72,46 @@ __global__ __launch_bounds__(256) void dgemm_nn(const double* __restrict__ A, in
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  double2 ra[4], rb[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    ra[i] = *reinterpret_cast<const double2*>(Ag + 2 * i);
-    rb[i] = *reinterpret_cast<const double2*>(Bg + 2 * i);
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    As[0][a_k + 2 * i][a_row] = ra[i].x;
-    As[0][a_k + 2 * i + 1][a_row] = ra[i].y;
-    *reinterpret_cast<double2*>(&Bs[0][b_k][b_n + 2 * i]) = rb[i];
-  }
-  __syncthreads();
+  // Stage helpers as macros so the staging registers stay in VGPRs.
+#define TD_LOAD_GLOBAL(kt)                                                     \
+  do {                                                                         \
+    const double* an_ = Ag + (size_t)(kt) * BK;                                \
+    const double* bn_ = Bg + (size_t)(kt) * BK * ldb;                          \
+    ra0 = *reinterpret_cast<const double2*>(an_ + 0);                          \
+    ra1 = *reinterpret_cast<const double2*>(an_ + 2);                          \
+    ra2 = *reinterpret_cast<const double2*>(an_ + 4);                          \
+    ra3 = *reinterpret_cast<const double2*>(an_ + 6);                          \
+    rb0 = *reinterpret_cast<const double2*>(bn_ + 0);                          \
+    rb1 = *reinterpret_cast<const double2*>(bn_ + 2);                          \
+    rb2 = *reinterpret_cast<const double2*>(bn_ + 4);                          \
+    rb3 = *reinterpret_cast<const double2*>(bn_ + 6);                          \
+  } while (0)
+#define TD_STORE_LDS(buf)                                                      \
+  do {                                                                         \
+    As[buf][a_k + 0][a_row] = ra0.x;                                           \
+    As[buf][a_k + 1][a_row] = ra0.y;                                           \
+    As[buf][a_k + 2][a_row] = ra1.x;                                           \
+    As[buf][a_k + 3][a_row] = ra1.y;                                           \
+    As[buf][a_k + 4][a_row] = ra2.x;                                           \
+    As[buf][a_k + 5][a_row] = ra2.y;                                           \
+    As[buf][a_k + 6][a_row] = ra3.x;                                           \
+    As[buf][a_k + 7][a_row] = ra3.y;                                           \
+    *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n + 0]) = rb0;                 \
+    *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n + 2]) = rb1;                 \
+    *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n + 4]) = rb2;                 \
+    *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n + 6]) = rb3;                 \
+  } while (0)
 
+  double2 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
   const int nk = K / BK;
+  TD_LOAD_GLOBAL(0);
+  TD_STORE_LDS(0);
+  __syncthreads();
+  // Steady state: the loads of stage kt+1 are in flight while stage kt computes.
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    const bool more = (kt + 1) < nk;
-    if (more) {
-      const double* an = Ag + (size_t)(kt + 1) * BK;
-      const double* bn = Bg + (size_t)(kt + 1) * BK * ldb;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        ra[i] = *reinterpret_cast<const double2*>(an + 2 * i);
-        rb[i] = *reinterpret_cast<const double2*>(bn + 2 * i);
-      }
-    }
+    const bool more = kt + 1 < nk;
+    if (more) TD_LOAD_GLOBAL(kt + 1);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kl = kk + lk;
@@ -113,33 +126,39 @@ __global__ __launch_bounds__(256) void dgemm_nn(const double* __restrict__ A, in
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (more) {
-      const int nxt = cur ^ 1;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        As[nxt][a_k + 2 * i][a_row] = ra[i].x;
-        As[nxt][a_k + 2 * i + 1][a_row] = ra[i].y;
-        *reinterpret_cast<double2*>(&Bs[nxt][b_k][b_n + 2 * i]) = rb[i];
-      }
-    }
+    if (more) TD_STORE_LDS(cur ^ 1);
     __syncthreads();
   }
+#undef TD_LOAD_GLOBAL
+#undef TD_STORE_LDS
 
   // Accumulator layout of the 16x16 f64 block: register r of lane l holds
   // row l/16 + 4 r, column l%16.
+  if (beta == 0.0) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int col = n0 + wn * 64 + j * 16 + l16;
+      for (int j = 0; j < 4; ++j) {
+        const int col = n0 + wn * 64 + j * 16 + l16;
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int row = m0 + wm * 64 + i * 16 + lk + 4 * rr;
-        double v = alpha * acc[i][j][rr];
-        if (beta != 0.0) v += beta * Cin[(size_t)row * ldcin + col];
-        C[(size_t)row * ldc + col] = v;
+        for (int rr = 0; rr < 4; ++rr) {
+          const int row = m0 + wm * 64 + i * 16 + lk + 4 * rr;
+          C[(size_t)row * ldc + col] = alpha * acc[i][j][rr];
+        }
       }
-    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = n0 + wn * 64 + j * 16 + l16;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int row = m0 + wm * 64 + i * 16 + lk + 4 * rr;
+          C[(size_t)row * ldc + col] =
+              alpha * acc[i][j][rr] + beta * Cin[(size_t)row * ldcin + col];
+        }
+      }
   }
 }
 
