@@ -2,17 +2,22 @@
 
 One step is the whole clamped-nuclei hot path on one density matrix:
 Mulliken charges, SCC potential with the laser field, Hamiltonian
-rebuild, S^-1 H, (S^-1 H)[Re rho | Im rho], leapfrog update and dipole.
-Workload: seeded synthetic C938H344 armchair strip (N_orb = 4096) from
-its SCC ground state, driven by a sin^2 laser (0.1 Ha, 0.005 au,
-in-plane transverse), dt = 0.2 au. The ground state is computed on the
-GPU and is not timed.
+rebuild, the two products of S^-1 H rho, the leapfrog update and the
+dipole. Workload: seeded synthetic C938H344 armchair strip (N_orb = 4096)
+from its SCC ground state (computed on the GPU, not timed), driven by a
+sin^2 laser (0.1 Ha, 0.005 au, in-plane transverse), dt = 0.2 au.
 
-Prints one JSON line. `roofline` is for the dominant kernel, the
-(S^-1 H)[Re rho | Im rho] product (4 n^3 algorithmic flop per launch),
-timed with HIP events on the library's stream over the timed steps.
-`cpu_baseline` times the CPU oracle on a bounded sample of the same
-workload.
+Both precisions run from the same ground state: FP64, and split-bf16 with
+S slices (error-free splitting, fp32 accumulation, fp64 combination). The
+split run is admissible only if its dipole stays within 1e-6 relative
+error of the FP64 run over the same steps; `value` is the faster
+admissible one.
+
+Prints one JSON line. `roofline` is for the dominant kernel of the
+reported precision, the product (S^-1 H)[Re rho | Im rho] (FP64: 4 n^3
+flop per launch) or its split form (issued bf16 flop per launch), timed
+with HIP events on the library's stream over the timed steps.
+`cpu_baseline` times the CPU oracle on a bounded sample of the workload.
 """
 from __future__ import annotations
 
@@ -29,7 +34,7 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
-HBM_PEAK_GBS = 8000.0
+DIPOLE_TOL = 1e-6
 
 
 def parse():
@@ -37,12 +42,53 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--precision", choices=["fp64"], default="fp64")
+    ap.add_argument("--precision", choices=["both", "fp64", "split"], default="both")
+    ap.add_argument("--slices", type=int, default=4, choices=[3, 4, 5])
     ap.add_argument("--cpu-steps", type=int, default=3,
                     help="oracle steps in the CPU-baseline sample (0 to skip)")
     ap.add_argument("--traffic", type=str, default="",
                     help="optional JSON file with measured HBM bytes per launch")
+    ap.add_argument("--validate", type=int, default=0,
+                    help="instead of timing: propagate this many steps in FP64 and in "
+                         "split-bf16 (--slices) from the same ground state and print the "
+                         "dipole relative error against FP64")
     return ap.parse_args()
+
+
+def validate(args):
+    """Dipole error of split-bf16 against FP64 over a long run of the workload."""
+    import workloads as W
+    from paper_1912_03174_amd import tddftb as T
+    w = W.workload(3)
+    n = args.validate
+    field = w.field(0, n)
+    chunk = 500
+    series = {}
+    for name, prec in (("fp64", T.TD_FP64), ("split", T.TD_SPLIT_BF16)):
+        p = T.Propagator(w.system, dt=w.dt, precision=prec, n_slices=args.slices, scc_tol=1e-10)
+        mus = []
+        t0 = time.perf_counter()
+        for k in range(0, n, chunk):
+            m = min(chunk, n - k)
+            mus.append(p.step(m, field[k:k + m]))
+            if (k // chunk) % 4 == 3:
+                log(f"{name}: {k + m} steps, {time.perf_counter() - t0:.1f} s")
+        p.close()
+        series[name] = np.concatenate(mus)
+    ref, got = series["fp64"], series["split"]
+    scale = np.abs(ref - ref[0]).max()
+    err = np.abs(got - ref).max(axis=1) / scale
+    marks = [m for m in (100, 500, 1000, 2000, 5000, 10000, 20000) if m <= n]
+    out = {"validate_steps": n, "slices": args.slices, "workload": "strip4096",
+           "dipole_rel_err": float(err.max()),
+           "dipole_rel_err_at": {str(m): float(err[:m].max()) for m in marks},
+           "admissible": bool(err.max() <= DIPOLE_TOL),
+           "signal_max_au": float(scale)}
+    print(json.dumps(out), flush=True)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def cpu_baseline(w, n_steps):
@@ -64,12 +110,63 @@ def cpu_baseline(w, n_steps):
     return {"value": n_steps / el, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n_steps} oracle leapfrog steps (charges, potential, H, three "
                       f"complex128 products, update) at N_orb={s.n_orb} on a seeded Hermitian "
-                      f"density, numpy/OpenBLAS; S^-1 formed before timing; "
-                      f"{el:.2f} s"}
+                      f"density near the neutral rho = 1, numpy/OpenBLAS; S^-1 formed before "
+                      f"timing; {el:.2f} s"}
+
+
+def run(T, w, precision, slices, warmup, steps, field):
+    s = w.system
+    n = s.n_orb
+    t0 = time.perf_counter()
+    p = T.Propagator(s, dt=w.dt, precision=precision, n_slices=slices, profile=True,
+                     scc_tol=1e-10)
+    init_s = time.perf_counter() - t0
+    info = p.info()
+    mus = []
+    if warmup:
+        mus.append(p.step(warmup, field[:warmup]))
+    p.reset_kernel_time()
+    t0 = time.perf_counter()
+    mus.append(p.step(steps, field[warmup:]))     # returns after the stream has drained
+    elapsed = time.perf_counter() - t0
+    times = {k: p.kernel_time(k) for k in range(4)}
+    p.close()
+    split = precision == T.TD_SPLIT_BF16
+    pairs = slices * (slices + 1) // 2
+    ms, cnt = times[T.TD_KT_GEMM_ARHO]
+    avg = ms / max(cnt, 1)
+    if split:
+        flop = pairs * 6.0 * n ** 3          # issued bf16: K = 2n real half, K = n imaginary half
+        peak = BF16_PEAK_TFLOPS
+        name = f"sgemm_split<{slices}>: [S^-1 H | S^-1 dH][rho - rho_ref ; rho_ref]"
+    else:
+        flop = 4.0 * n ** 3
+        peak = FP64_PEAK_TFLOPS
+        name = "dgemm_nn<2>: (S^-1 H)[Re rho | Im rho]"
+    achieved = flop / (avg * 1e-3) / 1e12
+    return {
+        "steps_per_s": steps / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "init_s": init_s,
+        "init": {k: info[k] for k in ("scc_iterations", "scc_residual",
+                                      "purification_iterations", "inverse_iterations")},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "kernel": name, "flop_per_launch": flop,
+                     "avg_launch_ms": avg, "launches": cnt},
+        "breakdown_ms": {"product_1": times[T.TD_KT_GEMM_SH][0] / max(times[0][1], 1),
+                         "product_2": avg,
+                         "update": times[T.TD_KT_UPDATE][0] / max(times[2][1], 1),
+                         "other": times[T.TD_KT_OTHER][0] / max(times[3][1], 1)},
+        "fp64_equivalent_tflops": 6.0 * n ** 3 * steps / elapsed / 1e12,
+        "dipoles": np.concatenate(mus),
+    }
 
 
 def main():
     args = parse()
+    if args.validate:
+        validate(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
@@ -79,72 +176,56 @@ def main():
 
     w = W.workload(3)
     s = w.system
-    n = s.n_orb
-    total = args.warmup + args.steps
-    field = w.field(0, total)
-
-    t0 = time.perf_counter()
-    p = T.Propagator(s, dt=w.dt, precision=T.TD_FP64, profile=True, scc_tol=1e-10)
-    init_s = time.perf_counter() - t0
-    info = p.info()
-
-    if args.warmup:
-        p.step(args.warmup, field[:args.warmup])
-    p.reset_kernel_time()
-    t0 = time.perf_counter()
-    p.step(args.steps, field[args.warmup:])      # returns after the stream has drained
-    elapsed = time.perf_counter() - t0
-    mu = p.dipole()
-    assert np.all(np.isfinite(mu))
-
-    steps_per_s = args.steps / elapsed
-    ms_step = 1e3 * elapsed / args.steps
-    arho_ms, arho_n = p.kernel_time(T.TD_KT_GEMM_ARHO)
-    sh_ms, sh_n = p.kernel_time(T.TD_KT_GEMM_SH)
-    up_ms, up_n = p.kernel_time(T.TD_KT_UPDATE)
-    ot_ms, ot_n = p.kernel_time(T.TD_KT_OTHER)
-    p.close()
-
-    flop_arho = 4.0 * n ** 3
-    avg_arho = arho_ms / max(arho_n, 1)
-    achieved = flop_arho / (avg_arho * 1e-3) / 1e12
+    field = w.field(0, args.warmup + args.steps)
+    res = {}
+    if args.precision in ("both", "fp64"):
+        log("fp64 run")
+        res["fp64"] = run(T, w, T.TD_FP64, args.slices, args.warmup, args.steps, field)
+    if args.precision in ("both", "split"):
+        log(f"split-bf16 x{args.slices} run")
+        res["split"] = run(T, w, T.TD_SPLIT_BF16, args.slices, args.warmup, args.steps, field)
+    if "fp64" in res and "split" in res:
+        ref = res["fp64"]["dipoles"]
+        err = float(np.abs(res["split"]["dipoles"] - ref).max() / np.abs(ref - ref[0]).max())
+        res["split"]["dipole_rel_err_vs_fp64"] = err
+        res["split"]["admissible"] = err <= DIPOLE_TOL
+    best = "fp64"
+    if "split" in res and (res["split"].get("admissible") or "fp64" not in res):
+        if "fp64" not in res or res["split"]["steps_per_s"] > res["fp64"]["steps_per_s"]:
+            best = "split"
+    if best not in res:
+        best = "split"
+    r = res[best]
     traffic = None
     if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
-    step_tflops = 6.0 * n ** 3 * steps_per_s / 1e12
-
+        traffic = json.load(open(args.traffic)).get(best, {}).get("bytes_per_launch")
+    roof = dict(r["roofline"])
+    roof["traffic"] = traffic
+    dtype = "f64" if best == "fp64" else f"bf16 (split x{args.slices}, fp32 accumulate, f64 combine)"
     out = {
         "metric": "density-matrix steps/s at N_orb=4096 (FP64 vs split-BF16 @1e-6 dipole err)",
-        "value": steps_per_s,
+        "value": r["steps_per_s"],
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": "strip4096", "system": "C938H344 armchair strip (seeded)",
-                   "n_orb": n, "n_atoms": s.n_atoms, "dt_au": w.dt,
+                   "n_orb": s.n_orb, "n_atoms": s.n_atoms, "dt_au": w.dt,
                    "field": "sin^2 laser 0.1 Ha, 0.005 au, in-plane transverse",
-                   "precision": "fp64", "parallelism": "single GPU"},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": "dgemm_nn<2>: (S^-1 H)[Re rho | Im rho], 4 n^3 flop/launch",
-                     "avg_launch_ms": avg_arho, "launches": arho_n},
-        "step_breakdown_ms": {"gemm_sinv_h": sh_ms / max(sh_n, 1), "gemm_a_rho": avg_arho,
-                              "leapfrog_update": up_ms / max(up_n, 1),
-                              "charges_potential_h": ot_ms / max(ot_n, 1)},
-        "step_fp64_tflops": step_tflops,
-        "step_fp64_frac": step_tflops / FP64_PEAK_TFLOPS,
-        "trajectory_fs_per_s": steps_per_s * w.dt * 0.0241888432658,
-        "init_s": init_s,
-        "init": {k: info[k] for k in ("scc_iterations", "scc_residual",
-                                      "purification_iterations", "inverse_iterations")},
+                   "precision": best, "parallelism": "single GPU"},
+        "roofline": roof,
+        "trajectory_fs_per_s": r["steps_per_s"] * w.dt * 0.0241888432658,
+        "precisions": {k: {kk: vv for kk, vv in v.items() if kk != "dipoles"}
+                       for k, v in res.items()},
     }
     if args.cpu_steps > 0:
+        log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)
 

@@ -113,7 +113,10 @@ typedef struct {
   int32_t precision;
 } td_info;
 
-/* Kernel classes timed when td_options.profile = 1. */
+/* Kernel classes timed when td_options.profile = 1. In split-bf16
+ * precision the two classes of products are S^-1 dH and
+ * [S^-1 H | S^-1 dH] [rho - rho_ref ; rho_ref], and the slicing kernels
+ * count as TD_KT_OTHER. */
 enum {
   TD_KT_GEMM_SH = 0,      /* S^-1 H product                 (2 n^3 flop) */
   TD_KT_GEMM_ARHO = 1,    /* (S^-1 H) [Re rho | Im rho]     (4 n^3 flop) */

@@ -38,10 +38,21 @@ hipError_t charges_dipole(hipStream_t s, const double* q_orb, const int* orb_off
                           const double* q0, const double* pos, int na, double* dq,
                           double* mu_out, double* ne_out);
 
-// v[a] = sum_c gamma[a, c] dq[c] + R_a . E (E may be null); vorb[u] = v[atom(u)].
+// v[a] = sum_c gamma[a, c] dq[c] + R_a . E (E may be null);
+// vorb[u] = v[atom(u)] - v_ref[atom(u)] (v_ref may be null).
 hipError_t potential(hipStream_t s, const double* gamma, const double* dq,
                      const double* pos, const double* E, const int* orb_off, int na,
-                     double* v, double* vorb);
+                     double* v, double* vorb, const double* v_ref = nullptr);
+
+// Split precision charges: q_u = q_delta[u] + (1 - c) q_ref[u] with the trace
+// correction c = (sum(q_delta + q_ref) - n_elec) / n_elec -> c_out[0];
+// dq, dipole as charges_dipole.
+hipError_t charges_dipole_split(hipStream_t s, const double* q_delta, const double* q_ref,
+                                const int* orb_off, const double* q0, const double* pos, int na,
+                                double n_elec, double* dq, double* mu_out, double* c_out);
+// Real block of a wide matrix += sign * R (np x np).
+hipError_t wide_add_real(hipStream_t s, double* W, const double* R, int np, double sign);
+hipError_t vec_add(hipStream_t s, const double* a, const double* b, double* out, int n);
 
 // H = H0 + 1/2 S o (vorb_u + vorb_v), n x n with leading dimension n.
 hipError_t assemble_h(hipStream_t s, const double* H0, const double* S, const double* vorb,

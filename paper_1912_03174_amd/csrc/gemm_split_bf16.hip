@@ -1,0 +1,380 @@
+// Split-BF16 matrix-core product (error-free splitting in the manner of
+// Ozaki, Ogita, Oishi and Rump, Numer. Algorithms 59 (2012)) for the
+// density-matrix step's two products (Sec. 2.3) at close to FP64 accuracy.
+//
+// Operands are cut into S bf16 slices with one power-of-two exponent per
+// row (left operand) or per column (right operand, stored transposed so k
+// is contiguous). Slices are stored k-blocked: row r holds, for each block
+// of 16 values of k, the S slices of that block one after another (32 S
+// bytes), so one K step of the product reads whole cache lines per row.
+// Row i of M is scaled by 2^-e_i (|M_ik| < 2^e_i) and
+// written as an integer series
+//     M_ik 2^-e_i 2^8 = sigma_1 + sigma_2 2^-8 + ... + sigma_S 2^-8(S-1) + rest,
+// each sigma_t an integer with |sigma_t| <= 256, rounded to nearest, and
+// stored as w_t = sigma_t 2^-8(t-1), exact in bf16 (8 significant bits).
+// A product of two slices is exact in fp32 (16 bits); so is the sum over
+// 256 values of k of the leading pair (1,1), accumulated on its own, and of
+// the two pairs (1,2), (2,1). Pairs with t_a + t_b <= S + 1 are kept.
+// Every 256 values of k (a chunk) the fp32 accumulators are added into an
+// fp64 accumulator with the row and column exponents of the current K
+// segment: one product may concatenate segments with different operand
+// scales along K (used for (S^-1 H) rho_delta + (S^-1 dH) rho_ref).
+#include <cmath>
+
+#include "common.hpp"
+#include "split.hpp"
+
+namespace td {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int CHUNK = 256;       // exact fp32 accumulation length of the leading pairs
+constexpr int GROUP_M = 8;
+
+template <int S>
+struct SplitArgs {
+  const __bf16* L;      // [M][ldl], k-blocked slices
+  int ldl;
+  const int* eL;        // [nseg][M]
+  int eL_stride;
+  const __bf16* R;      // [Ncols][ldr] (transposed right operand), k-blocked slices
+  int ldr;
+  const int* fR;        // [nseg][Ncols]
+  int fR_stride;
+  int seg_len;          // K length of one segment (multiple of CHUNK)
+  int k_lo, k_hi;       // K extent for tiles with n0 >= n_split / n0 < n_split
+  int n_split;
+  double* C;
+  int ldc;
+  const double* Cin;    // optional addend (same layout as C), may be null
+  int ldcin;
+  int tiles_m, tiles_n;
+};
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// s_waitcnt with only the vector-memory counter constrained (gfx9 encoding:
+// vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt[15:14]).
+#define TD_WAIT_VMCNT(n) __builtin_amdgcn_s_waitcnt(((n) & 15) | (7 << 4) | (15 << 8) | (((n) >> 4) << 14))
+
+// LDS stage layout: [mat][slice][row][16 k] bf16 (32 B per row). The two
+// 16-byte halves of row r are swapped when bit 2 of r differs from bit 3, so
+// the b128 fragment reads of consecutive rows hit distinct bank groups.
+// The global slices are k-blocked, so the S loads of one 32-row block for a
+// K step touch the same 32 cache lines, back to back.
+__device__ __forceinline__ int half_swz(int row) { return ((row >> 2) ^ (row >> 3)) & 1; }
+
+template <int S>
+__global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
+  // LDS ring of STAGES separate arrays (so the compiler can see that the
+  // direct-to-LDS loads into one stage do not alias the fragment reads of
+  // another, and does not wait for them); loads run STAGES-1 stages ahead.
+  constexpr int STAGES = S <= 4 ? 4 : 2;
+  constexpr int MAT_ELEMS = S * 128 * BK;                  // one operand tile per stage
+  constexpr int STAGE_ELEMS = 2 * MAT_ELEMS;
+  __shared__ __attribute__((aligned(1024))) __bf16 st0[STAGE_ELEMS];
+  __shared__ __attribute__((aligned(1024))) __bf16 st1[STAGE_ELEMS];
+  __shared__ __attribute__((aligned(1024))) __bf16 st2[STAGES > 2 ? STAGE_ELEMS : 8];
+  __shared__ __attribute__((aligned(1024))) __bf16 st3[STAGES > 2 ? STAGE_ELEMS : 8];
+  __shared__ int sh_e[2][BM], sh_f[2][BN];                // segment exponents of the tile
+
+  const int nt = p.tiles_m * p.tiles_n;
+  const int w = blockIdx.x;
+  const int q = nt >> 3, r = nt & 7;
+  const int xcd = w & 7, slot = w >> 3;
+  const int lin = xcd * q + (xcd < r ? xcd : r) + slot;
+  const int group = GROUP_M * p.tiles_n;
+  const int g = lin / group;
+  const int first_m = g * GROUP_M;
+  const int gsz = (p.tiles_m - first_m) < GROUP_M ? (p.tiles_m - first_m) : GROUP_M;
+  const int in_g = lin - g * group;
+  const int m0 = (first_m + in_g % gsz) * BM;
+  const int n0 = (in_g / gsz) * BN;
+  const int K = (n0 < p.n_split) ? p.k_hi : p.k_lo;
+  const int nk = K / BK;
+
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;      // 4 x 2 waves: 32 rows x 64 columns each
+  const int l32 = lane & 31, lh = lane >> 5;
+
+  // A stage is 8 S direct-to-LDS instructions of 64 x 16 B, S per wave.
+  // Instruction gi: operand gi / (4S), slice (gi / 4) % S, 32-row block gi % 4;
+  // lane L fills row L/2, half L%2 of that block.
+  constexpr int PER_WAVE = S;
+  const __bf16* src_base[PER_WAVE];
+  int lds_off[PER_WAVE];
+#pragma unroll
+  for (int c = 0; c < PER_WAVE; ++c) {
+    const int gi = wave + 8 * c;
+    const int mat = gi / (4 * S);
+    const int sl = (gi >> 2) % S;
+    const int row = (gi & 3) * 32 + (lane >> 1);
+    const int ghalf = (lane & 1) ^ half_swz(row);
+    src_base[c] = mat ? (p.R + (size_t)(n0 + row) * p.ldr + sl * 16 + ghalf * 8)
+                      : (p.L + (size_t)(m0 + row) * p.ldl + sl * 16 + ghalf * 8);
+    lds_off[c] = mat * MAT_ELEMS + (sl * 4 + (gi & 3)) * 512;
+  }
+#define TD_ISSUE_STAGE(BUF, kt)                                                            \
+  do {                                                                                     \
+    _Pragma("unroll") for (int c = 0; c < PER_WAVE; ++c) {                                 \
+      __builtin_amdgcn_global_load_lds(                                                    \
+          (const void*)(src_base[c] + (size_t)(kt) * (BK * S)),                            \
+          (lds_void*)((BUF) + lds_off[c]), 16, 0, 0);                                      \
+    }                                                                                      \
+  } while (0)
+
+  // acc2: pair (1,1), exact over a chunk; acc3: every other kept pair. Its
+  // leading terms (1,2), (2,1) are 2^-8 of acc2 and exact on their own; the
+  // smaller pairs added to them round at about 2^-32 of the leading term.
+  f32x16 acc2[2], acc3[2];
+  double acc64[2][16];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      acc2[j][e] = 0.0f;
+      acc3[j][e] = 0.0f;
+      acc64[j][e] = 0.0;
+    }
+  }
+  // segment exponents of this tile's rows and columns, staged once in LDS
+  const int nseg = (p.k_hi > p.seg_len) ? 2 : 1;
+  for (int i = t; i < nseg * BM; i += 512) {
+    const int sg = i / BM, rr = i % BM;
+    sh_e[sg][rr] = p.eL[sg * p.eL_stride + m0 + rr];
+    sh_f[sg][rr] = p.fR[sg * p.fR_stride + n0 + rr];
+  }
+
+  // Output layout of the 32x32 fp32 block: register e of lane l holds row
+  // 8 (e/4) + 4 (l/32) + e%4, column l%32.
+#define TD_SPLIT_FLUSH(k_chunk_start)                                                      \
+  {                                                                                        \
+    const int seg = (k_chunk_start) / p.seg_len;                                           \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                        \
+      const int fc = sh_f[seg][wn * 64 + j * 32 + l32] - 16;                               \
+      _Pragma("unroll") for (int e = 0; e < 16; ++e) {                                     \
+        const int sc = sh_e[seg][wm * 32 + 8 * (e >> 2) + 4 * lh + (e & 3)] + fc;          \
+        acc64[j][e] += ldexp((double)acc2[j][e] + (double)acc3[j][e], sc);                 \
+        acc2[j][e] = 0.0f;                                                                 \
+        acc3[j][e] = 0.0f;                                                                 \
+      }                                                                                    \
+    }                                                                                      \
+  }
+
+  __syncthreads();     // exponents visible before any flush; no loads in flight yet
+  // prologue: stages 0 .. STAGES-2 in flight
+  TD_ISSUE_STAGE(st0, 0);
+  if (STAGES > 2) {
+    TD_ISSUE_STAGE(st1, 1);
+    TD_ISSUE_STAGE(st2, 2);
+  }
+
+  // fragment offsets (elements) inside a stage
+  int a_off[S], b_off[2][S];
+  {
+    const int arow = wm * 32 + l32;
+#pragma unroll
+    for (int sl = 0; sl < S; ++sl) a_off[sl] = sl * 128 * BK + arow * BK + ((lh ^ half_swz(arow)) * 8);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int brow = wn * 64 + j * 32 + l32;
+#pragma unroll
+      for (int sl = 0; sl < S; ++sl)
+        b_off[j][sl] = MAT_ELEMS + sl * 128 * BK + brow * BK + ((lh ^ half_swz(brow)) * 8);
+    }
+  }
+  // One K step on stage RD: wait for this wave's loads of it, barrier (all
+  // waves' loads landed and all waves are past the previous step), refill
+  // slot WR (the stage consumed in the previous step) STAGES-1 ahead, then
+  // the matrix cores. The plain s_barrier carries no memory fence, so the
+  // loads of later stages stay in flight across it.
+#define TD_SPLIT_STEP(RD, WR, kt, FLUSH_OK)                                                \
+  {                                                                                        \
+    const int ahead = (nk - 1 - (kt)) < (STAGES - 2) ? (nk - 1 - (kt)) : (STAGES - 2);    \
+    if (ahead >= 2) {                                                                      \
+      TD_WAIT_VMCNT(2 * PER_WAVE);                                                         \
+    } else if (ahead == 1) {                                                               \
+      TD_WAIT_VMCNT(PER_WAVE);                                                             \
+    } else {                                                                               \
+      TD_WAIT_VMCNT(0);                                                                    \
+    }                                                                                      \
+    __builtin_amdgcn_s_barrier();                                                          \
+    if ((kt) + STAGES - 1 < nk) TD_ISSUE_STAGE(WR, (kt) + STAGES - 1);                     \
+    bf16x8 a[S], b[2][S];                                                                  \
+    _Pragma("unroll") for (int sl = 0; sl < S; ++sl) {                                     \
+      a[sl] = *reinterpret_cast<const bf16x8*>((RD) + a_off[sl]);                          \
+      _Pragma("unroll") for (int j = 0; j < 2; ++j)                                        \
+        b[j][sl] = *reinterpret_cast<const bf16x8*>((RD) + b_off[j][sl]);                  \
+    }                                                                                      \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j)                                          \
+      acc2[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[j][0], acc2[j], 0, 0, 0);  \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j)                                          \
+      acc3[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[j][1], acc3[j], 0, 0, 0);  \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j)                                          \
+      acc3[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[j][0], acc3[j], 0, 0, 0);  \
+    _Pragma("unroll") for (int sa = 0; sa < S; ++sa)                                       \
+      _Pragma("unroll") for (int sb = 0; sb < S; ++sb)                                     \
+        if (sa + sb >= 2 && sa + sb <= S - 1)                                              \
+          _Pragma("unroll") for (int j = 0; j < 2; ++j)                                    \
+            acc3[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[sa], b[j][sb], acc3[j], 0, \
+                                                              0, 0);                       \
+    if (FLUSH_OK) {                                                                        \
+      const int k_next = ((kt) + 1) * BK;                                                  \
+      if (k_next % CHUNK == 0 || (kt) + 1 == nk) TD_SPLIT_FLUSH((kt) * BK - ((kt) * BK) % CHUNK) \
+    }                                                                                      \
+  }
+
+  // nk is a multiple of CHUNK / BK = 16, so of STAGES; flushes fall on the
+  // last step of each unrolled group.
+  for (int kt = 0; kt < nk; kt += STAGES) {
+    if (STAGES == 4) {
+      TD_SPLIT_STEP(st0, st3, kt, false)
+      TD_SPLIT_STEP(st1, st0, kt + 1, false)
+      TD_SPLIT_STEP(st2, st1, kt + 2, false)
+      TD_SPLIT_STEP(st3, st2, kt + 3, true)
+    } else {
+      TD_SPLIT_STEP(st0, st1, kt, false)
+      TD_SPLIT_STEP(st1, st0, kt + 1, true)
+    }
+  }
+#undef TD_SPLIT_STEP
+#undef TD_ISSUE_STAGE
+#undef TD_SPLIT_FLUSH
+
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int col = n0 + wn * 64 + j * 32 + l32;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int row = m0 + wm * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
+      double v = acc64[j][e];
+      if (p.Cin) v += p.Cin[(size_t)row * p.ldcin + col];
+      p.C[(size_t)row * p.ldc + col] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ slicing
+// One wave per row: exponent e with max |x| < 2^e (0 for a zero row), then S
+// rounded slices of x 2^-e 2^8, stored pre-scaled as sigma_t 2^-8(t-1).
+template <int S, int MODE>
+__global__ __launch_bounds__(256) void k_slice_rows(SliceSrc src, int rows, int cols,
+                                                    __bf16* out, int ldo, int* exps) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (row >= rows) return;
+  auto value = [&](int c) -> double {
+    if (MODE == SLICE_PLAIN) return src.sign * src.M0[(size_t)row * src.ld0 + c];
+    if (MODE == SLICE_SUM)
+      return src.M0[(size_t)row * src.ld0 + c] + src.M1[(size_t)row * src.ld1 + c];
+    if (MODE == SLICE_RENORM)
+      return src.M0[(size_t)row * src.ld0 + c] - src.cs[0] * src.M1[(size_t)row * src.ld1 + c];
+    // SLICE_DH: 1/2 S_uv (dv_u + dv_v)
+    return 0.5 * src.M0[(size_t)row * src.ld0 + c] * (src.v[row] + src.v[c]);
+  };
+  double m = 0.0;
+  for (int c = l; c < cols; c += 64) m = fmax(m, fabs(value(c)));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  int e = 0;
+  if (m > 0.0) {
+    frexp(m, &e);          // m = f 2^e, f in [0.5, 1): max |x| < 2^e
+  }
+  if (l == 0) exps[row] = e;
+  for (int c = l; c < cols; c += 64) {
+    const double x = value(c);
+    if (MODE == SLICE_RENORM) src.M0w[(size_t)row * src.ld0 + c] = x;
+    double rr = ldexp(x, 8 - e);    // |rr| < 256
+    __bf16* o = out + (size_t)row * ldo + (size_t)(c >> 4) * (16 * S) + (c & 15);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const double sig = rint(rr);
+      o[s * 16] = (__bf16)(float)ldexp(sig, -8 * s);
+      rr = (rr - sig) * 256.0;
+    }
+  }
+}
+
+template <int S>
+hipError_t launch_split(hipStream_t st, const SplitGemm& g) {
+  SplitArgs<S> p;
+  p.L = g.L;
+  p.ldl = g.ldl;
+  p.eL = g.eL;
+  p.eL_stride = g.eL_stride;
+  p.R = g.R;
+  p.ldr = g.ldr;
+  p.fR = g.fR;
+  p.fR_stride = g.fR_stride;
+  p.seg_len = g.seg_len;
+  p.k_lo = g.k_lo;
+  p.k_hi = g.k_hi;
+  p.n_split = g.n_split;
+  p.C = g.C;
+  p.ldc = g.ldc;
+  p.Cin = g.Cin;
+  p.ldcin = g.ldcin;
+  p.tiles_m = g.m / BM;
+  p.tiles_n = g.n / BN;
+  hipLaunchKernelGGL(sgemm_split<S>, dim3(p.tiles_m * p.tiles_n), dim3(512), 0, st, p);
+  return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch_slice(hipStream_t st, int mode, const SliceSrc& src, int rows, int cols,
+                        __bf16* out, int ldo, int* exps) {
+  const dim3 grid((rows + 3) / 4), block(256);
+  switch (mode) {
+    case SLICE_PLAIN:
+      hipLaunchKernelGGL((k_slice_rows<S, SLICE_PLAIN>), grid, block, 0, st, src, rows, cols, out,
+                         ldo, exps);
+      break;
+    case SLICE_SUM:
+      hipLaunchKernelGGL((k_slice_rows<S, SLICE_SUM>), grid, block, 0, st, src, rows, cols, out,
+                         ldo, exps);
+      break;
+    case SLICE_DH:
+      hipLaunchKernelGGL((k_slice_rows<S, SLICE_DH>), grid, block, 0, st, src, rows, cols, out,
+                         ldo, exps);
+      break;
+    case SLICE_RENORM:
+      hipLaunchKernelGGL((k_slice_rows<S, SLICE_RENORM>), grid, block, 0, st, src, rows, cols,
+                         out, ldo, exps);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t split_gemm(hipStream_t st, int n_slices, const SplitGemm& g) {
+  if (g.m % BM || g.n % BN || g.m <= 0 || g.n <= 0) return hipErrorInvalidValue;
+  if (g.seg_len % CHUNK || g.k_lo % CHUNK || g.k_hi % CHUNK || g.k_lo <= 0 || g.k_hi <= 0)
+    return hipErrorInvalidValue;
+  if (g.ldl % (16 * n_slices) || g.ldr % (16 * n_slices)) return hipErrorInvalidValue;
+  switch (n_slices) {
+    case 3: return launch_split<3>(st, g);
+    case 4: return launch_split<4>(st, g);
+    case 5: return launch_split<5>(st, g);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t slice_rows(hipStream_t st, int n_slices, int mode, const SliceSrc& src, int rows,
+                      int cols, __bf16* out, int ldo, int* exps) {
+  if (cols % 16) return hipErrorInvalidValue;
+  switch (n_slices) {
+    case 3: return launch_slice<3>(st, mode, src, rows, cols, out, ldo, exps);
+    case 4: return launch_slice<4>(st, mode, src, rows, cols, out, ldo, exps);
+    case 5: return launch_slice<5>(st, mode, src, rows, cols, out, ldo, exps);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace td

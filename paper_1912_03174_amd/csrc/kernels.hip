@@ -128,7 +128,8 @@ __global__ __launch_bounds__(256) void k_potential(const double* __restrict__ ga
                                                    const double* __restrict__ E,
                                                    const int* __restrict__ off, int na,
                                                    double* __restrict__ v,
-                                                   double* __restrict__ vorb) {
+                                                   double* __restrict__ vorb,
+                                                   const double* __restrict__ v_ref) {
   const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int l = threadIdx.x & 63;
   if (a >= na) return;
@@ -138,7 +139,8 @@ __global__ __launch_bounds__(256) void k_potential(const double* __restrict__ ga
   acc = wave_sum(acc);
   if (E) acc += pos[3 * a] * E[0] + pos[3 * a + 1] * E[1] + pos[3 * a + 2] * E[2];
   if (l == 0) v[a] = acc;
-  for (int u = off[a] + l; u < off[a + 1]; u += WAVE) vorb[u] = acc;
+  const double vo = v_ref ? acc - v_ref[a] : acc;
+  for (int u = off[a] + l; u < off[a + 1]; u += WAVE) vorb[u] = vo;
 }
 
 // ------------------------------------------------------------------ H assembly
@@ -504,6 +506,54 @@ __global__ __launch_bounds__(1024) void k_energy(const double* __restrict__ band
   }
 }
 
+// Split precision: populations q = q_delta + q_ref; the electron count
+// N(t) = sum q gives the trace correction c = (N(t) - n_elec) / n_elec,
+// applied as rho <- rho - c rho_ref (linear, so q <- q - c q_ref).
+__global__ __launch_bounds__(1024) void k_charges_dipole_split(
+    const double* __restrict__ q_delta, const double* __restrict__ q_ref,
+    const int* __restrict__ off, const double* __restrict__ q0, const double* __restrict__ pos,
+    int na, double n_elec, double* __restrict__ dq, double* __restrict__ mu_out,
+    double* __restrict__ c_out) {
+  __shared__ double sh[17];
+  double ne = 0.0;
+  for (int a = threadIdx.x; a < na; a += 1024)
+    for (int u = off[a]; u < off[a + 1]; ++u) ne += q_delta[u] + q_ref[u];
+  ne = block_sum_1024(ne, sh);
+  const double c = (ne - n_elec) / n_elec;
+  double mx = 0.0, my = 0.0, mz = 0.0;
+  for (int a = threadIdx.x; a < na; a += 1024) {
+    double q = 0.0;
+    for (int u = off[a]; u < off[a + 1]; ++u) q += q_delta[u] + (1.0 - c) * q_ref[u];
+    const double d = q - q0[a];
+    dq[a] = d;
+    mx -= d * pos[3 * a + 0];
+    my -= d * pos[3 * a + 1];
+    mz -= d * pos[3 * a + 2];
+  }
+  mx = block_sum_1024(mx, sh);
+  my = block_sum_1024(my, sh);
+  mz = block_sum_1024(mz, sh);
+  if (threadIdx.x == 0) {
+    mu_out[0] = mx;
+    mu_out[1] = my;
+    mu_out[2] = mz;
+    c_out[0] = c;
+  }
+}
+
+__global__ void k_wide_add_real(double* W, const double* __restrict__ R, int np, double sign) {
+  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (size_t)np * np) return;
+  const int r = (int)(idx / np), c = (int)(idx % np);
+  W[(size_t)r * 2 * np + c] += sign * R[idx];
+}
+
+__global__ void k_vec_add(const double* __restrict__ a, const double* __restrict__ b,
+                          double* __restrict__ out, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = a[i] + b[i];
+}
+
 inline unsigned blocks_for(size_t n, int per = 256) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -525,9 +575,29 @@ hipError_t charges_dipole(hipStream_t s, const double* q_orb, const int* orb_off
 }
 
 hipError_t potential(hipStream_t s, const double* gamma, const double* dq, const double* pos,
-                     const double* E, const int* orb_off, int na, double* v, double* vorb) {
+                     const double* E, const int* orb_off, int na, double* v, double* vorb,
+                     const double* v_ref) {
   hipLaunchKernelGGL(k_potential, dim3((na + 3) / 4), dim3(256), 0, s, gamma, dq, pos, E,
-                     orb_off, na, v, vorb);
+                     orb_off, na, v, vorb, v_ref);
+  return hipGetLastError();
+}
+
+hipError_t charges_dipole_split(hipStream_t s, const double* q_delta, const double* q_ref,
+                                const int* orb_off, const double* q0, const double* pos, int na,
+                                double n_elec, double* dq, double* mu_out, double* c_out) {
+  hipLaunchKernelGGL(k_charges_dipole_split, dim3(1), dim3(1024), 0, s, q_delta, q_ref, orb_off,
+                     q0, pos, na, n_elec, dq, mu_out, c_out);
+  return hipGetLastError();
+}
+
+hipError_t wide_add_real(hipStream_t s, double* W, const double* R, int np, double sign) {
+  hipLaunchKernelGGL(k_wide_add_real, dim3(blocks_for((size_t)np * np)), dim3(256), 0, s, W, R,
+                     np, sign);
+  return hipGetLastError();
+}
+
+hipError_t vec_add(hipStream_t s, const double* a, const double* b, double* out, int n) {
+  hipLaunchKernelGGL(k_vec_add, dim3(blocks_for((size_t)n)), dim3(256), 0, s, a, b, out, n);
   return hipGetLastError();
 }
 

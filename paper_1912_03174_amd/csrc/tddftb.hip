@@ -21,6 +21,7 @@
 
 #include "../../include/tddftb.h"
 #include "common.hpp"
+#include "split.hpp"
 
 using td::round_up;
 
@@ -49,6 +50,18 @@ struct td_ctx {
   int last_n = 0;
   td_info info{};
   std::string err;
+  // split-bf16 precision: the state buffers hold rho - rho_ref
+  bool split = false;
+  int ns = 4;
+  double *rho_ref = nullptr;   // np x np real reference density (the initial state)
+  double *Agsb = nullptr;      // S^-1 H_ref
+  double *Xref = nullptr;      // np x 2np wide: (S^-1 H_ref) rho_ref | 0
+  double *q_ref = nullptr;     // np: Mulliken row sums of rho_ref
+  double *v_ref = nullptr;     // na: SCC potential of rho_ref
+  double *band_ref = nullptr;  // np: row sums of rho_ref o H0
+  double *stage = nullptr;     // np x 2np scratch
+  __bf16 *sl_sinv = nullptr, *sl_dh = nullptr, *sl_L2 = nullptr, *sl_R2 = nullptr;
+  int *e_sinv = nullptr, *e_dh = nullptr, *e_L2 = nullptr, *e_R2 = nullptr;
   // profiling
   std::vector<hipEvent_t> ev;
   double kt_ms[TD_KT_COUNT] = {0, 0, 0, 0};
@@ -59,7 +72,7 @@ namespace {
 
 // scal[] slots
 enum { SC_MU = 0, SC_NE = 3, SC_RES = 4, SC_TR1 = 5, SC_TR2 = 6, SC_BOUNDS = 8, SC_E = 10,
-       SC_FIELD = 16, SC_COUNT = 32 };
+       SC_RENORM = 13, SC_FIELD = 16, SC_COUNT = 32 };
 
 struct Fail {
   td_status st;
@@ -120,6 +133,22 @@ void free_all(td_ctx* c) {
     if (*b) hipFree(*b);
     *b = nullptr;
   }
+  double** sbufs[] = {&c->rho_ref, &c->Agsb, &c->Xref, &c->q_ref, &c->v_ref, &c->band_ref,
+                      &c->stage};
+  for (double** b : sbufs) {
+    if (*b) hipFree(*b);
+    *b = nullptr;
+  }
+  __bf16** slb[] = {&c->sl_sinv, &c->sl_dh, &c->sl_L2, &c->sl_R2};
+  for (__bf16** b : slb) {
+    if (*b) hipFree(*b);
+    *b = nullptr;
+  }
+  int** eb[] = {&c->e_sinv, &c->e_dh, &c->e_L2, &c->e_R2};
+  for (int** b : eb) {
+    if (*b) hipFree(*b);
+    *b = nullptr;
+  }
   if (c->orb_off) hipFree(c->orb_off);
   c->orb_off = nullptr;
   for (hipEvent_t e : c->ev) hipEventDestroy(e);
@@ -145,8 +174,15 @@ void gemm(td_ctx* c, int tag, int m, int n, int k, double alpha, const double* A
 // (device, 3 doubles).
 void mulliken(td_ctx* c, double* mu) {
   HIPCHK(c, td::rowdot(c->stream, c->rho_cur, 2 * c->np, c->S, c->np, c->q_orb, c->np, c->np));
-  HIPCHK(c, td::charges_dipole(c->stream, c->q_orb, c->orb_off, c->q0, c->pos, c->na, c->dq, mu,
-                               c->scal + SC_NE));
+  if (c->split) {
+    // rho = rho_ref + delta; trace correction c -> scal[SC_RENORM]
+    HIPCHK(c, td::charges_dipole_split(c->stream, c->q_orb, c->q_ref, c->orb_off, c->q0, c->pos,
+                                       c->na, (double)c->nelec, c->dq, mu,
+                                       c->scal + SC_RENORM));
+  } else {
+    HIPCHK(c, td::charges_dipole(c->stream, c->q_orb, c->orb_off, c->q0, c->pos, c->na, c->dq,
+                                 mu, c->scal + SC_NE));
+  }
 }
 
 // Observables of the current state, copied to the host; checks finiteness.
@@ -294,7 +330,8 @@ void validate(td_ctx* c, const td_system* s, const td_options* o) {
   REQUIRE(c, o->dt > 0 && std::isfinite(o->dt), TD_EINVAL, "dt must be positive");
   REQUIRE(c, o->precision == TD_FP64 || o->precision == TD_SPLIT_BF16, TD_EINVAL,
           "unknown precision");
-  REQUIRE(c, o->precision == TD_FP64, TD_ENOTSUP, "split-bf16 precision is not available");
+  REQUIRE(c, o->precision == TD_FP64 || (o->n_slices >= 3 && o->n_slices <= 5), TD_EINVAL,
+          "n_slices must be 3, 4 or 5");
   REQUIRE(c, o->scc_tol > 0 && o->scc_maxiter > 0 && o->mix_beta > 0 && o->mix_beta <= 1,
           TD_EINVAL, "invalid SCC options");
   const size_t n = (size_t)s->n_orb, na = (size_t)s->n_atoms;
@@ -313,6 +350,160 @@ void validate(td_ctx* c, const td_system* s, const td_options* o) {
   if (s->rho0) REQUIRE(c, finite_all(s->rho0, 2 * n * n), TD_EINVAL, "non-finite rho0");
 }
 
+void salloc(td_ctx* c, __bf16** p, size_t count) {
+  HIPCHK(c, hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(__bf16)));
+  HIPCHK(c, hipMemsetAsync(*p, 0, std::max<size_t>(count, 1) * sizeof(__bf16), c->stream));
+}
+
+void ialloc(td_ctx* c, int** p, size_t count) {
+  HIPCHK(c, hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(int)));
+  HIPCHK(c, hipMemsetAsync(*p, 0, std::max<size_t>(count, 1) * sizeof(int), c->stream));
+}
+
+void slice(td_ctx* c, int mode, const td::SliceSrc& src, int rows, int cols, __bf16* out,
+           int ldo, int* exps) {
+  HIPCHK(c, td::slice_rows(c->stream, c->ns, mode, src, rows, cols, out, ldo, exps));
+}
+
+// Split precision set-up. The current (full) density becomes the reference
+// rho_ref (its real part) and the state holds delta = rho - rho_ref. With
+// A_ref = S^-1 H_ref and B = S^-1 dH (dH = H - H_ref, from dv = v - v_ref),
+//   X = S^-1 H rho = A_ref rho_ref + (A_ref + B) delta + B rho_ref,
+// so the products act on O(signal) operands and the O(1) part A_ref rho_ref
+// is formed once in FP64.
+void split_init(td_ctx* c) {
+  const int n = c->n, np = c->np, na = c->na;
+  const size_t m2 = (size_t)np * np;
+  dalloc(c, &c->rho_ref, m2);
+  dalloc(c, &c->Agsb, m2);
+  dalloc(c, &c->Xref, 2 * m2);
+  dalloc(c, &c->q_ref, np);
+  dalloc(c, &c->v_ref, na);
+  dalloc(c, &c->band_ref, np);
+  dalloc(c, &c->stage, 2 * m2);
+  salloc(c, &c->sl_sinv, (size_t)c->ns * m2);
+  salloc(c, &c->sl_dh, (size_t)c->ns * m2);
+  salloc(c, &c->sl_L2, (size_t)c->ns * 2 * m2);
+  salloc(c, &c->sl_R2, (size_t)c->ns * 4 * m2);
+  ialloc(c, &c->e_sinv, np);
+  ialloc(c, &c->e_dh, np);
+  ialloc(c, &c->e_L2, 2 * (size_t)np);
+  ialloc(c, &c->e_R2, 4 * (size_t)np);
+  hipStream_t st = c->stream;
+  HIPCHK(c, td::pair_sym(st, c->rho_cur, 2 * np, c->rho_ref, nullptr, np, np));
+  HIPCHK(c, td::wide_add_real(st, c->rho_cur, c->rho_ref, np, -1.0));
+  HIPCHK(c, td::rowdot(st, c->rho_ref, np, c->S, np, c->q_ref, np, np));
+  HIPCHK(c, td::rowdot(st, c->rho_ref, np, c->H0, np, c->band_ref, np, np));
+  HIPCHK(c, td::charges_dipole(st, c->q_ref, c->orb_off, c->q0, c->pos, na, c->dq,
+                               c->scal + SC_MU, c->scal + SC_NE));
+  HIPCHK(c, td::potential(st, c->gamma, c->dq, c->pos, nullptr, c->orb_off, na, c->v_ref,
+                          c->vorb));
+  HIPCHK(c, td::assemble_h(st, c->H0, c->S, c->vorb, c->H, np));
+  gemm(c, 0, np, np, np, 1.0, c->Sinv, np, c->H, np, c->Agsb, np);
+  gemm(c, 0, np, np, np, 1.0, c->Agsb, np, c->rho_ref, np, c->Xref, 2 * np);
+  td::SliceSrc si;
+  si.M0 = c->Sinv;
+  si.ld0 = np;
+  const int S = c->ns;
+  slice(c, td::SLICE_PLAIN, si, np, np, c->sl_sinv, np * S, c->e_sinv);
+  td::SliceSrc sr;
+  sr.M0 = c->rho_ref;
+  sr.ld0 = np;
+  // reference rows become K segment 1 of the second product's right operand
+  slice(c, td::SLICE_PLAIN, sr, np, np, c->sl_R2 + (size_t)np * S, 2 * np * S,
+        c->e_R2 + 2 * np);
+  (void)n;
+}
+
+// One split-precision step body (after the dipole of rho_k is recorded):
+// potential change, sliced dH, B = S^-1 dH, sliced [A | B] and
+// [delta_re + renorm | -delta_im], X = A_ref rho_ref + [A | B][delta; rho_ref].
+void split_products(td_ctx* c, const double* E, hipEvent_t* ev) {
+  const int np = c->np, na = c->na;
+  const size_t m2 = (size_t)np * np;
+  hipStream_t st = c->stream;
+  HIPCHK(c, td::potential(st, c->gamma, c->dq, c->pos, E, c->orb_off, na, c->v, c->vorb,
+                          c->v_ref));
+  td::SliceSrc sdh;
+  sdh.M0 = c->S;
+  sdh.ld0 = np;
+  sdh.v = c->vorb;
+  const int S = c->ns;
+  slice(c, td::SLICE_DH, sdh, np, np, c->sl_dh, np * S, c->e_dh);
+  td::SplitGemm g1;
+  g1.m = np;
+  g1.n = np;
+  g1.L = c->sl_sinv;
+  g1.ldl = np * S;
+  g1.eL = c->e_sinv;
+  g1.R = c->sl_dh;
+  g1.ldr = np * S;
+  g1.fR = c->e_dh;
+  g1.seg_len = np;
+  g1.k_lo = np;
+  g1.k_hi = np;
+  g1.n_split = np;
+  g1.C = c->H;            // B = S^-1 dH
+  g1.ldc = np;
+  if (ev) HIPCHK(c, hipEventRecord(ev[1], st));
+  HIPCHK(c, td::split_gemm(st, c->ns, g1));
+  if (ev) HIPCHK(c, hipEventRecord(ev[2], st));
+  td::SliceSrc sa;
+  sa.M0 = c->Agsb;
+  sa.ld0 = np;
+  sa.M1 = c->H;
+  sa.ld1 = np;
+  slice(c, td::SLICE_SUM, sa, np, np, c->sl_L2, 2 * np * S, c->e_L2);
+  td::SliceSrc sb;
+  sb.M0 = c->H;
+  sb.ld0 = np;
+  slice(c, td::SLICE_PLAIN, sb, np, np, c->sl_L2 + (size_t)np * S, 2 * np * S, c->e_L2 + np);
+  td::SliceSrc sdr;
+  sdr.M0 = c->rho_cur;
+  sdr.M0w = c->rho_cur;
+  sdr.ld0 = 2 * np;
+  sdr.M1 = c->rho_ref;
+  sdr.ld1 = np;
+  sdr.cs = c->scal + SC_RENORM;
+  slice(c, td::SLICE_RENORM, sdr, np, np, c->sl_R2, 2 * np * S, c->e_R2);
+  td::SliceSrc sdi;
+  sdi.M0 = c->rho_cur + np;
+  sdi.ld0 = 2 * np;
+  sdi.sign = -1.0;
+  slice(c, td::SLICE_PLAIN, sdi, np, np, c->sl_R2 + (size_t)np * 2 * np * S, 2 * np * S,
+        c->e_R2 + np);
+  td::SplitGemm g2;
+  g2.m = np;
+  g2.n = 2 * np;
+  g2.L = c->sl_L2;
+  g2.ldl = 2 * np * S;
+  g2.eL = c->e_L2;
+  g2.eL_stride = np;
+  g2.R = c->sl_R2;
+  g2.ldr = 2 * np * S;
+  g2.fR = c->e_R2;
+  g2.fR_stride = 2 * np;
+  g2.seg_len = np;
+  g2.k_hi = 2 * np;     // real columns: A delta_re + B rho_ref
+  g2.k_lo = np;         // imaginary columns: A delta_im
+  g2.n_split = np;
+  g2.C = c->X;
+  g2.ldc = 2 * np;
+  g2.Cin = c->Xref;
+  g2.ldcin = 2 * np;
+  if (ev) HIPCHK(c, hipEventRecord(ev[3], st));
+  HIPCHK(c, td::split_gemm(st, c->ns, g2));
+  if (ev) HIPCHK(c, hipEventRecord(ev[4], st));
+}
+
+// Full density (rho_ref + delta in split precision) of `src` into the wide `dst`.
+void full_density(td_ctx* c, const double* src, double* dst) {
+  if (dst != src)
+    HIPCHK(c, hipMemcpyAsync(dst, src, sizeof(double) * 2 * (size_t)c->np * c->np,
+                             hipMemcpyDeviceToDevice, c->stream));
+  if (c->split) HIPCHK(c, td::wide_add_real(c->stream, dst, c->rho_ref, c->np, 1.0));
+}
+
 void upload_padded(td_ctx* c, const double* host, int n, double* dev, int np) {
   HIPCHK(c, hipMemcpy2DAsync(dev, sizeof(double) * np, host, sizeof(double) * n,
                              sizeof(double) * n, n, hipMemcpyHostToDevice, c->stream));
@@ -327,7 +518,12 @@ void create_impl(td_ctx* c, const td_system* s, const td_options* o) {
   c->opt = *o;
   c->na = s->n_atoms;
   c->n = s->n_orb;
-  c->np = round_up(s->n_orb, td::kPad);
+  // c->split switches on only after split_init: the ground state and the
+  // inverse run in FP64 and need the reference buffers not yet allocated.
+  const bool want_split = o->precision == TD_SPLIT_BF16;
+  c->ns = o->n_slices;
+  // split products accumulate exactly over 256-long K chunks
+  c->np = round_up(s->n_orb, want_split ? 256 : td::kPad);
   c->nelec = s->n_elec;
   const int na = c->na, n = c->n, np = c->np;
   if (o->hip_stream) {
@@ -383,6 +579,10 @@ void create_impl(td_ctx* c, const td_system* s, const td_options* o) {
   } else {
     ground_state(c);
   }
+  if (want_split) {
+    split_init(c);
+    c->split = true;
+  }
   c->step = 0;
   c->has_prev = false;
   refresh(c);
@@ -411,22 +611,28 @@ void step_impl(td_ctx* c, int nsteps, const double* field) {
     HIPCHK(c, hipMemcpyAsync(c->field, field, sizeof(double) * 3 * nsteps, hipMemcpyHostToDevice,
                              c->stream));
   const bool prof = c->opt.profile != 0;
-  if (prof) ensure_events(c, 5 * (size_t)nsteps);
+  // events per step: start | G1 | G1 end | G2 | G2 end | update end
+  if (prof) ensure_events(c, 6 * (size_t)nsteps);
   hipStream_t st = c->stream;
   for (int k = 0; k < nsteps; ++k) {
-    hipEvent_t* e = prof ? &c->ev[5 * (size_t)k] : nullptr;
+    hipEvent_t* e = prof ? &c->ev[6 * (size_t)k] : nullptr;
     if (prof) HIPCHK(c, hipEventRecord(e[0], st));
     // charges and dipole of rho_k, SCC potential, Hamiltonian (Eqs. 5-7)
     mulliken(c, c->dip + 3 * (size_t)k);
-    HIPCHK(c, td::potential(st, c->gamma, c->dq, c->pos, field ? c->field + 3 * (size_t)k : nullptr,
-                            c->orb_off, na, c->v, c->vorb));
-    HIPCHK(c, td::assemble_h(st, c->H0, c->S, c->vorb, c->H, np));
-    if (prof) HIPCHK(c, hipEventRecord(e[1], st));
-    // X = S^-1 H rho (Eq. 10), as A = S^-1 H then A [Re rho | Im rho]
-    gemm(c, 1, np, np, np, 1.0, c->Sinv, np, c->H, np, c->A, np);
-    if (prof) HIPCHK(c, hipEventRecord(e[2], st));
-    gemm(c, 2, np, 2 * np, np, 1.0, c->A, np, c->rho_cur, 2 * np, c->X, 2 * np);
-    if (prof) HIPCHK(c, hipEventRecord(e[3], st));
+    const double* Ek = field ? c->field + 3 * (size_t)k : nullptr;
+    if (c->split) {
+      split_products(c, Ek, e);
+    } else {
+      HIPCHK(c, td::potential(st, c->gamma, c->dq, c->pos, Ek, c->orb_off, na, c->v, c->vorb));
+      HIPCHK(c, td::assemble_h(st, c->H0, c->S, c->vorb, c->H, np));
+      if (prof) HIPCHK(c, hipEventRecord(e[1], st));
+      // X = S^-1 H rho (Eq. 10), as A = S^-1 H then A [Re rho | Im rho]
+      gemm(c, 1, np, np, np, 1.0, c->Sinv, np, c->H, np, c->A, np);
+      if (prof) HIPCHK(c, hipEventRecord(e[2], st));
+      if (prof) HIPCHK(c, hipEventRecord(e[3], st));
+      gemm(c, 2, np, 2 * np, np, 1.0, c->A, np, c->rho_cur, 2 * np, c->X, 2 * np);
+      if (prof) HIPCHK(c, hipEventRecord(e[4], st));
+    }
     // rho_{k+1} = rho_{k-1} + 2 dt rhodot (Eq. 19); Euler start without history
     if (c->has_prev) {
       HIPCHK(c, td::pair_leapfrog(st, c->X, c->X + np, 2 * np, c->rho_prev, c->rho_prev + np,
@@ -438,23 +644,20 @@ void step_impl(td_ctx* c, int nsteps, const double* field) {
       c->has_prev = true;
     }
     std::swap(c->rho_cur, c->rho_prev);
-    if (prof) HIPCHK(c, hipEventRecord(e[4], st));
+    if (prof) HIPCHK(c, hipEventRecord(e[5], st));
     c->step += 1;
   }
   c->last_n = nsteps;
   refresh(c);
   if (prof) {
     for (int k = 0; k < nsteps; ++k) {
-      hipEvent_t* e = &c->ev[5 * (size_t)k];
-      float ms[4];
-      HIPCHK(c, hipEventElapsedTime(&ms[0], e[0], e[1]));
-      HIPCHK(c, hipEventElapsedTime(&ms[1], e[1], e[2]));
-      HIPCHK(c, hipEventElapsedTime(&ms[2], e[2], e[3]));
-      HIPCHK(c, hipEventElapsedTime(&ms[3], e[3], e[4]));
-      c->kt_ms[TD_KT_OTHER] += ms[0];
+      hipEvent_t* e = &c->ev[6 * (size_t)k];
+      float ms[5];
+      for (int q = 0; q < 5; ++q) HIPCHK(c, hipEventElapsedTime(&ms[q], e[q], e[q + 1]));
+      c->kt_ms[TD_KT_OTHER] += ms[0] + ms[2];
       c->kt_ms[TD_KT_GEMM_SH] += ms[1];
-      c->kt_ms[TD_KT_GEMM_ARHO] += ms[2];
-      c->kt_ms[TD_KT_UPDATE] += ms[3];
+      c->kt_ms[TD_KT_GEMM_ARHO] += ms[3];
+      c->kt_ms[TD_KT_UPDATE] += ms[4];
       for (int q = 0; q < TD_KT_COUNT; ++q) c->kt_n[q] += 1;
     }
   }
@@ -473,15 +676,81 @@ void kick_impl(td_ctx* c, double e0, const double* dir) {
   }
   HIPCHK(c, hipMemcpyAsync(c->xorb, x.data(), sizeof(double) * np, hipMemcpyHostToDevice,
                            c->stream));
-  // rho(0+) = 1/2 (T + T^+), T = S^-1 K S rho K^+ (Sec. 2.2, Eq. 16)
-  gemm(c, 0, np, 2 * np, np, 1.0, c->S, np, c->rho_cur, 2 * np, c->X, 2 * np);
+  // rho(0+) = 1/2 (T + T^+), T = S^-1 K S rho K^+ (Sec. 2.2, Eq. 16), in FP64
+  const double* full = c->rho_cur;
+  if (c->split) {
+    full_density(c, c->rho_cur, c->stage);
+    full = c->stage;
+  }
+  gemm(c, 0, np, 2 * np, np, 1.0, c->S, np, full, 2 * np, c->X, 2 * np);
   HIPCHK(c, td::kick_phase(c->stream, c->X, c->X + np, 2 * np, c->xorb, np, e0));
   gemm(c, 0, np, 2 * np, np, 1.0, c->Sinv, np, c->X, 2 * np, c->rho_prev, 2 * np);
   HIPCHK(c, td::pair_herm(c->stream, c->rho_prev, c->rho_prev + np, 2 * np, c->rho_cur,
                           c->rho_cur + np, 2 * np, np));
+  if (c->split) HIPCHK(c, td::wide_add_real(c->stream, c->rho_cur, c->rho_ref, np, -1.0));
   c->has_prev = false;
   sync(c);
   refresh(c);
+}
+
+// Host-pointer split-bf16 product for td_util_gemm: A rows and B columns
+// (B transposed on the host) are sliced on the device.
+void split_gemm_host(td_ctx* c, int ns, int m, int n, int k, const double* A, const double* B,
+                     double* C) {
+  const int mp = round_up(m, 128), npd = round_up(n, 128), kp = round_up(k, 256);
+  std::vector<double> bt((size_t)n * k);
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < n; ++j) bt[(size_t)j * k + i] = B[(size_t)i * n + j];
+  dalloc(c, &c->S, (size_t)mp * kp);
+  dalloc(c, &c->H, (size_t)npd * kp);
+  dalloc(c, &c->A, (size_t)mp * npd);
+  HIPCHK(c, hipMemcpy2DAsync(c->S, sizeof(double) * kp, A, sizeof(double) * k,
+                             sizeof(double) * k, m, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpy2DAsync(c->H, sizeof(double) * kp, bt.data(), sizeof(double) * k,
+                             sizeof(double) * k, n, hipMemcpyHostToDevice, c->stream));
+  __bf16 *ls = nullptr, *rs = nullptr;
+  int *el = nullptr, *fr = nullptr;
+  const size_t lsz = (size_t)mp * kp, rsz = (size_t)npd * kp;
+  HIPCHK(c, hipMalloc((void**)&ls, sizeof(__bf16) * lsz * ns));
+  HIPCHK(c, hipMalloc((void**)&rs, sizeof(__bf16) * rsz * ns));
+  HIPCHK(c, hipMalloc((void**)&el, sizeof(int) * mp));
+  HIPCHK(c, hipMalloc((void**)&fr, sizeof(int) * npd));
+  struct Free {
+    void* p[4];
+    ~Free() {
+      for (void* q : p)
+        if (q) hipFree(q);
+    }
+  } guard{{ls, rs, el, fr}};
+  td::SliceSrc sa;
+  sa.M0 = c->S;
+  sa.ld0 = kp;
+  HIPCHK(c, td::slice_rows(c->stream, ns, td::SLICE_PLAIN, sa, mp, kp, ls, kp * ns, el));
+  td::SliceSrc sb;
+  sb.M0 = c->H;
+  sb.ld0 = kp;
+  HIPCHK(c, td::slice_rows(c->stream, ns, td::SLICE_PLAIN, sb, npd, kp, rs, kp * ns, fr));
+  td::SplitGemm g;
+  g.m = mp;
+  g.n = npd;
+  g.L = ls;
+  g.ldl = kp * ns;
+  g.eL = el;
+  g.eL_stride = 0;
+  g.R = rs;
+  g.ldr = kp * ns;
+  g.fR = fr;
+  g.fR_stride = 0;
+  g.seg_len = kp;
+  g.k_lo = kp;
+  g.k_hi = kp;
+  g.n_split = npd;
+  g.C = c->A;
+  g.ldc = npd;
+  HIPCHK(c, td::split_gemm(c->stream, ns, g));
+  HIPCHK(c, hipMemcpy2DAsync(C, sizeof(double) * n, c->A, sizeof(double) * npd,
+                             sizeof(double) * n, m, hipMemcpyDeviceToHost, c->stream));
+  sync(c);
 }
 
 }  // namespace
@@ -569,6 +838,7 @@ td_status td_get_energy(td_ctx* ctx, const double field[3], double* energy) {
       HIPCHK(c, hipMemcpyAsync(c->scal + SC_FIELD, field, sizeof(double) * 3,
                                hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, td::rowdot(c->stream, c->rho_cur, 2 * c->np, c->H0, c->np, c->work1, c->np, c->np));
+    if (c->split) HIPCHK(c, td::vec_add(c->stream, c->work1, c->band_ref, c->work1, c->np));
     HIPCHK(c, td::potential(c->stream, c->gamma, c->dq, c->pos, nullptr, c->orb_off, c->na, c->v,
                             c->vorb));
     HIPCHK(c, td::energy_terms(c->stream, c->work1, c->np, c->dq, c->v, c->pos,
@@ -584,14 +854,25 @@ td_status td_get_rho(td_ctx* ctx, double* rho, double* rho_prev, int64_t* step,
   return guarded(ctx, [&] {
     td_ctx* c = ctx;
     const size_t n2 = (size_t)c->n * c->n;
+    const double* cur = c->rho_cur;
+    if (c->split) {
+      full_density(c, c->rho_cur, c->stage);
+      cur = c->stage;
+    }
     if (rho) {
-      HIPCHK(c, td::wide_to_interleaved(c->stream, c->rho_cur, c->np, c->X, c->n));
+      HIPCHK(c, td::wide_to_interleaved(c->stream, cur, c->np, c->X, c->n));
       HIPCHK(c, hipMemcpyAsync(rho, c->X, sizeof(double) * 2 * n2, hipMemcpyDeviceToHost,
                                c->stream));
     }
     if (rho_prev) {
       REQUIRE(c, c->has_prev, TD_ESTATE, "no previous density matrix (next step is Euler)");
-      HIPCHK(c, td::wide_to_interleaved(c->stream, c->rho_prev, c->np, c->X, c->n));
+      const double* prev = c->rho_prev;
+      if (c->split) {
+        sync(c);
+        full_density(c, c->rho_prev, c->stage);
+        prev = c->stage;
+      }
+      HIPCHK(c, td::wide_to_interleaved(c->stream, prev, c->np, c->X, c->n));
       HIPCHK(c, hipMemcpyAsync(rho_prev, c->X, sizeof(double) * 2 * n2, hipMemcpyDeviceToHost,
                                c->stream));
     }
@@ -611,10 +892,13 @@ td_status td_set_rho(td_ctx* ctx, const double* rho, const double* rho_prev, int
     HIPCHK(c, hipMemcpyAsync(c->X, rho, sizeof(double) * 2 * n2, hipMemcpyHostToDevice,
                              c->stream));
     HIPCHK(c, td::interleaved_to_wide(c->stream, c->X, c->n, c->rho_cur, c->np));
+    if (c->split) HIPCHK(c, td::wide_add_real(c->stream, c->rho_cur, c->rho_ref, c->np, -1.0));
     if (rho_prev) {
       HIPCHK(c, hipMemcpyAsync(c->X, rho_prev, sizeof(double) * 2 * n2, hipMemcpyHostToDevice,
                                c->stream));
       HIPCHK(c, td::interleaved_to_wide(c->stream, c->X, c->n, c->rho_prev, c->np));
+      if (c->split)
+        HIPCHK(c, td::wide_add_real(c->stream, c->rho_prev, c->rho_ref, c->np, -1.0));
     }
     c->has_prev = rho_prev != nullptr;
     c->step = step;
@@ -687,13 +971,19 @@ td_status td_util_gemm(int32_t precision, int32_t n_slices, int32_t m, int32_t n
   td_ctx* c = &tmp;
   td_status st = guarded(c, [&] {
     REQUIRE(c, A && B && C && m > 0 && n > 0 && k > 0, TD_EINVAL, "invalid gemm arguments");
-    REQUIRE(c, precision == TD_FP64, TD_ENOTSUP, "only FP64 products are available");
-    (void)n_slices;
+    REQUIRE(c, precision == TD_FP64 || precision == TD_SPLIT_BF16, TD_EINVAL,
+            "unknown precision");
+    REQUIRE(c, precision == TD_FP64 || (n_slices >= 3 && n_slices <= 5), TD_EINVAL,
+            "n_slices must be 3, 4 or 5");
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     REQUIRE(c, e == hipSuccess && ndev > 0, TD_EHIP, "no HIP device available");
     HIPCHK(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     c->own_stream = true;
+    if (precision == TD_SPLIT_BF16) {
+      split_gemm_host(c, n_slices, m, n, k, A, B, C);
+      return;
+    }
     const int mp = round_up(m, td::kGemmTile), npd = round_up(n, td::kGemmTile),
               kp = round_up(k, td::kGemmTile);
     dalloc(c, &c->S, (size_t)mp * kp);

@@ -1,0 +1,148 @@
+"""Split-bf16 precision (through the C ABI) against FP64 references.
+
+The split product is checked against numpy's FP64 product with the error
+bound of S slices of 8 bits: |error| <= 2^-(8S-2) k max_k|A_ik| max_k|B_kj|
+for S = 3 and the fp32-merge floor 2^-30 k max|A_i.| max|B_.j| for S >= 4.
+The propagation is checked against the CPU oracle with the dipole relative
+error target of 1e-6.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _T():
+    from paper_1912_03174_amd import tddftb as T
+    return T
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dipole_rel_err(test, ref):
+    ref = np.asarray(ref)
+    return np.abs(np.asarray(test) - ref).max() / np.abs(ref - ref[0]).max()
+
+
+@pytest.mark.parametrize("ns", [3, 4, 5])
+@pytest.mark.parametrize("m,k,n", [(1, 1, 1), (130, 300, 77), (512, 1024, 384)])
+def test_split_gemm_error_bound(ns, m, k, n):
+    T = _T()
+    say(f"split gemm s={ns} {m}x{k}x{n}")
+    rng = np.random.default_rng(m + 3 * k + 7 * n)
+    # rows and columns spanning many binades, as the scaled operands do
+    A = rng.standard_normal((m, k)) * np.exp2(rng.integers(-20, 20, size=(m, 1)))
+    B = rng.standard_normal((k, n)) * np.exp2(rng.integers(-20, 20, size=(1, n)))
+    C = T.td_util_gemm(A, B, precision=T.TD_SPLIT_BF16, n_slices=ns)
+    ref = A @ B
+    scale = k * np.abs(A).max(axis=1)[:, None] * np.abs(B).max(axis=0)[None, :]
+    bound = 2.0 ** -(8 * ns - 2) if ns == 3 else 2.0 ** -30
+    assert (np.abs(C - ref) / scale).max() <= bound
+
+
+def test_split_gemm_exact_on_small_integers():
+    T = _T()
+    A = np.eye(256)
+    B = np.repeat(np.arange(256.0)[:, None], 256, axis=1) + 1000.0 * np.arange(256)[None, :]
+    assert np.array_equal(T.td_util_gemm(A, B, precision=T.TD_SPLIT_BF16, n_slices=4), B)
+
+
+@pytest.fixture(scope="module")
+def flake():
+    s = W.flake_c24h16()
+    gs = O.ground_state(s, tol=1e-13)
+    Sinv = O.inverse_overlap(s.S)
+    return s, gs, Sinv
+
+
+def test_split_flake_kick_500_steps(flake):
+    T = _T()
+    s, gs, Sinv = flake
+    say("split flake 500 steps")
+    rk = O.kick(gs.rho, s.S, Sinv, s.positions, s.orb_offset, 1e-3, (1.0, 0.0, 0.0))
+    ref = O.propagate(s, rk, 500, 0.2, Sinv=Sinv, record_energy=False)
+    p = T.Propagator(s, rho0=gs.rho, precision=T.TD_SPLIT_BF16, n_slices=4)
+    p.kick(1e-3, (1.0, 0.0, 0.0))
+    mu = p.step(500)
+    err = dipole_rel_err(mu, ref.dipoles)
+    say(f"split flake dipole relative error {err:.3e}")
+    assert err < 1e-6
+    dq_ref = O.charge_fluctuations(ref.rho, s.S, s.orb_offset, s.q0)
+    assert np.abs(p.charges() - dq_ref).max() < 1e-6 * np.abs(dq_ref - gs.dq).max() + 1e-12
+    rho = p.rho()[0]
+    assert np.abs(rho - rho.conj().T).max() == 0.0
+    # renormalised at the start of every step; one step's rounding drift remains
+    assert abs(np.real(np.trace(rho @ s.S)) - s.n_elec) < 1e-10
+    p.close()
+
+
+def test_split_flake_laser_and_energy(flake):
+    T = _T()
+    s, gs, Sinv = flake
+    say("split flake laser")
+    n = 300
+    field = W.sin2_pulse(np.arange(n + 1) * 0.2, 0.005, 0.1, n * 0.2, (0.3, 1.0, 0.0))
+    ref = O.propagate(s, gs.rho, n, 0.2, Sinv=Sinv, field=field[:n])
+    p = T.Propagator(s, precision=T.TD_SPLIT_BF16, n_slices=4, scc_tol=1e-13)
+    mu = p.step(n, field[:n])
+    assert dipole_rel_err(mu, ref.dipoles) < 1e-6
+    dq_ref = O.charge_fluctuations(ref.rho, s.S, s.orb_offset, s.q0)
+    e_ref = O.energy(ref.rho, s.H0, s.gamma, dq_ref, s.positions, field[n])
+    assert abs(p.energy(field[n]) - e_ref) < 1e-9 * abs(e_ref)
+    p.close()
+
+
+def test_split_checkpoint_round_trip(flake):
+    T = _T()
+    s, gs, _ = flake
+    say("split checkpoint")
+    a = T.Propagator(s, rho0=gs.rho, precision=T.TD_SPLIT_BF16)
+    a.kick(1e-3, (0.0, 1.0, 0.0))
+    a.step(40)
+    rho, prev, step, _ = a.rho(with_prev=True)
+    mu_a = a.step(40)
+    b = T.Propagator(s, rho0=gs.rho, precision=T.TD_SPLIT_BF16)
+    b.set_rho(rho, prev, step)
+    mu_b = b.step(40)
+    # the checkpoint holds rho_ref + delta; restoring forms (rho_ref + delta) - rho_ref,
+    # equal to delta only to rounding, and the split products then round differently
+    signal = np.abs(mu_a - mu_a[0]).max()
+    assert np.abs(mu_a - mu_b).max() < 1e-8 * signal
+    a.close()
+    b.close()
+
+
+def test_split_full_size_one_step_sampled_rows():
+    """N_orb = 4096 in the benchmark's configuration, one split step, sampled rows."""
+    T = _T()
+    w = W.workload(3)
+    s = w.system
+    n = s.n_orb
+    say("split full size 4096 sampled rows")
+    r1, i1 = W.random_hermitian_pair(n, seed=41, scale=1e-3, base=np.eye(n))
+    r0, i0 = W.random_hermitian_pair(n, seed=42, scale=1e-3, base=np.eye(n))
+    cur, prev = r1 + 1j * i1, r0 + 1j * i0
+    # exact electron count, so the split path's trace renormalisation is a no-op
+    cur *= s.n_elec / np.sum(cur.real * s.S)
+    E = np.array([[0.0, 0.004, 0.0]])
+    p = T.Propagator(s, rho0=cur, precision=T.TD_SPLIT_BF16, n_slices=4)
+    p.set_rho(cur, prev, 10)
+    p.step(1, E)
+    new = p.rho()[0]
+    Sinv = O.inverse_overlap(s.S)
+    dq = O.charge_fluctuations(cur, s.S, s.orb_offset, s.q0)
+    V = O.external_potential(s.positions, E[0])
+    H = O.scc_hamiltonian_fast(s.H0, s.S, s.gamma, dq, s.orb_offset, V)
+    rows = np.random.default_rng(0).choice(n, size=16, replace=False)
+    ref = O.leapfrog_step(prev[rows], O.rho_dot_rows(cur, H, Sinv, rows), w.dt)
+    step_size = np.abs(ref - prev[rows]).max()
+    assert np.abs(new[rows] - ref).max() < 1e-7 * step_size
+    p.close()
