@@ -48,6 +48,9 @@ def parse():
                     help="oracle steps in the CPU-baseline sample (0 to skip)")
     ap.add_argument("--traffic", type=str, default="",
                     help="optional JSON file with measured HBM bytes per launch")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy this many bytes device-to-device once (a plain copy "
+                         "kernel of known size, to calibrate HBM byte counters)")
     ap.add_argument("--validate", type=int, default=0,
                     help="instead of timing: propagate this many steps in FP64 and in "
                          "split-bf16 (--slices) from the same ground state and print the "
@@ -164,6 +167,15 @@ def run(T, w, precision, slices, warmup, steps, field):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        import torch
+        a = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
     if args.validate:
         validate(args)
         return

@@ -60,12 +60,11 @@ typedef __attribute__((address_space(3))) void lds_void;
 // vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt[15:14]).
 #define TD_WAIT_VMCNT(n) __builtin_amdgcn_s_waitcnt(((n) & 15) | (7 << 4) | (15 << 8) | (((n) >> 4) << 14))
 
-// LDS stage layout: [mat][slice][row][16 k] bf16 (32 B per row). The two
-// 16-byte halves of row r are swapped when bit 2 of r differs from bit 3, so
-// the b128 fragment reads of consecutive rows hit distinct bank groups.
-// The global slices are k-blocked, so the S loads of one 32-row block for a
-// K step touch the same 32 cache lines, back to back.
-__device__ __forceinline__ int half_swz(int row) { return ((row >> 2) ^ (row >> 3)) & 1; }
+// LDS stage layout: [mat][row][2S slots of 8 bf16] -- one K step of the
+// k-blocked global layout, so each direct-to-LDS instruction moves whole
+// 128-byte lines (S = 4) -- with the slots of row r rotated by
+// f(r) = r + r/8 to spread the b128 fragment reads over the banks.
+__device__ __forceinline__ int rot(int row) { return row + (row >> 3); }
 
 template <int S>
 __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
@@ -73,7 +72,8 @@ __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
   // direct-to-LDS loads into one stage do not alias the fragment reads of
   // another, and does not wait for them); loads run STAGES-1 stages ahead.
   constexpr int STAGES = S <= 4 ? 4 : 2;
-  constexpr int MAT_ELEMS = S * 128 * BK;                  // one operand tile per stage
+  constexpr int SLOTS = 2 * S;                             // 16-byte slots per row per K step
+  constexpr int MAT_ELEMS = 128 * SLOTS * 8;               // one operand tile per stage
   constexpr int STAGE_ELEMS = 2 * MAT_ELEMS;
   __shared__ __attribute__((aligned(1024))) __bf16 st0[STAGE_ELEMS];
   __shared__ __attribute__((aligned(1024))) __bf16 st1[STAGE_ELEMS];
@@ -102,8 +102,8 @@ __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
   const int l32 = lane & 31, lh = lane >> 5;
 
   // A stage is 8 S direct-to-LDS instructions of 64 x 16 B, S per wave.
-  // Instruction gi: operand gi / (4S), slice (gi / 4) % S, 32-row block gi % 4;
-  // lane L fills row L/2, half L%2 of that block.
+  // Instruction gi: operand gi / (4S); its lane covers linear slot
+  // qq = (gi % 4S) * 64 + lane = row * 2S + physical slot.
   constexpr int PER_WAVE = S;
   const __bf16* src_base[PER_WAVE];
   int lds_off[PER_WAVE];
@@ -111,12 +111,14 @@ __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
   for (int c = 0; c < PER_WAVE; ++c) {
     const int gi = wave + 8 * c;
     const int mat = gi / (4 * S);
-    const int sl = (gi >> 2) % S;
-    const int row = (gi & 3) * 32 + (lane >> 1);
-    const int ghalf = (lane & 1) ^ half_swz(row);
-    src_base[c] = mat ? (p.R + (size_t)(n0 + row) * p.ldr + sl * 16 + ghalf * 8)
-                      : (p.L + (size_t)(m0 + row) * p.ldl + sl * 16 + ghalf * 8);
-    lds_off[c] = mat * MAT_ELEMS + (sl * 4 + (gi & 3)) * 512;
+    const int li = gi % (4 * S);
+    const int qq = li * 64 + lane;
+    const int row = qq / SLOTS;
+    const int ph = qq % SLOTS;
+    const int lg = (ph + rot(row)) % SLOTS;               // logical slot fetched
+    src_base[c] = mat ? (p.R + (size_t)(n0 + row) * p.ldr + lg * 8)
+                      : (p.L + (size_t)(m0 + row) * p.ldl + lg * 8);
+    lds_off[c] = mat * MAT_ELEMS + li * 512;
   }
 #define TD_ISSUE_STAGE(BUF, kt)                                                            \
   do {                                                                                     \
@@ -173,18 +175,23 @@ __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
     TD_ISSUE_STAGE(st2, 2);
   }
 
-  // fragment offsets (elements) inside a stage
+  // fragment offsets (elements) inside a stage: logical slot 2 s + lh of a row
   int a_off[S], b_off[2][S];
   {
     const int arow = wm * 32 + l32;
 #pragma unroll
-    for (int sl = 0; sl < S; ++sl) a_off[sl] = sl * 128 * BK + arow * BK + ((lh ^ half_swz(arow)) * 8);
+    for (int sl = 0; sl < S; ++sl) {
+      const int ph = ((2 * sl + lh - rot(arow)) % SLOTS + SLOTS) % SLOTS;
+      a_off[sl] = arow * SLOTS * 8 + ph * 8;
+    }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int brow = wn * 64 + j * 32 + l32;
 #pragma unroll
-      for (int sl = 0; sl < S; ++sl)
-        b_off[j][sl] = MAT_ELEMS + sl * 128 * BK + brow * BK + ((lh ^ half_swz(brow)) * 8);
+      for (int sl = 0; sl < S; ++sl) {
+        const int ph = ((2 * sl + lh - rot(brow)) % SLOTS + SLOTS) % SLOTS;
+        b_off[j][sl] = MAT_ELEMS + brow * SLOTS * 8 + ph * 8;
+      }
     }
   }
   // One K step on stage RD: wait for this wave's loads of it, barrier (all
