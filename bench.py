@@ -35,6 +35,11 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
 DIPOLE_TOL = 1e-6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_strip4096.json")
+COPY_PROBE_BYTES = 1 << 30
+# dominant kernel of each precision: (kernel name stem, source file)
+DOMINANT = {"fp64": ("dgemm_nn<2>", "paper_1912_03174_amd/csrc/gemm_f64.hip"),
+            "split": ("sgemm_split<", "paper_1912_03174_amd/csrc/gemm_split_bf16.hip")}
 
 
 def parse():
@@ -46,11 +51,16 @@ def parse():
     ap.add_argument("--slices", type=int, default=4, choices=[3, 4, 5])
     ap.add_argument("--cpu-steps", type=int, default=3,
                     help="oracle steps in the CPU-baseline sample (0 to skip)")
-    ap.add_argument("--traffic", type=str, default="",
-                    help="optional JSON file with measured HBM bytes per launch")
-    ap.add_argument("--copy-probe", type=int, default=0,
-                    help="only copy this many bytes device-to-device once (a plain copy "
-                         "kernel of known size, to calibrate HBM byte counters)")
+    ap.add_argument("--traffic", type=str, default=TRAFFIC_FILE,
+                    help="JSON file with the measured HBM bytes per launch of the dominant "
+                         "kernels (reported only while the kernel source is unchanged)")
+    ap.add_argument("--traffic-from", type=str, default="",
+                    help="host only: read rocprofv3 --pmc csv output (pmc_FETCH_SIZE, "
+                         "pmc_WRITE_SIZE, pmccopy_FETCH_SIZE, pmccopy_WRITE_SIZE under this "
+                         "folder) and write the --traffic file")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device-to-device once (a plain copy kernel of "
+                         "known size, to calibrate HBM byte counters)")
     ap.add_argument("--validate", type=int, default=0,
                     help="instead of timing: propagate this many steps in FP64 and in "
                          "split-bf16 (--slices) from the same ground state and print the "
@@ -88,6 +98,68 @@ def validate(args):
            "admissible": bool(err.max() <= DIPOLE_TOL),
            "signal_max_au": float(scale)}
     print(json.dumps(out), flush=True)
+
+
+def source_digest(rel):
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _pmc(folder, counter):
+    """[(kernel name, grid size, counter value KiB)] of one rocprofv3 --pmc csv run."""
+    import csv
+    path = os.path.join(folder, "run_counter_collection.csv")
+    with open(path) as f:
+        return [(r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"]))
+                for r in csv.DictReader(f) if r["Counter_Name"] == counter]
+
+
+def write_traffic(root, out_path):
+    """HBM bytes per launch of the dominant kernels from FETCH_SIZE / WRITE_SIZE runs.
+
+    Each counter is scaled by bytes / counter of a plain device-to-device copy
+    of COPY_PROBE_BYTES (read once, written once) measured with the same
+    counter. The split path's dominant kernel is the larger-grid launch of
+    sgemm_split (the second product)."""
+    cal = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        rows = [v for k, g, v in _pmc(os.path.join(root, "pmccopy_" + ctr), ctr)
+                if "copyBuffer" in k]
+        if len(rows) != 1:
+            raise SystemExit(f"expected one copy kernel in pmccopy_{ctr}, found {len(rows)}")
+        cal[ctr] = {"kib": rows[0], "factor": COPY_PROBE_BYTES / (rows[0] * 1024.0)}
+    out = {"workload": "strip4096", "copy_probe_bytes": COPY_PROBE_BYTES, "calibration": cal}
+    for prec, (stem, src) in DOMINANT.items():
+        per = {}
+        for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+            rows = [(g, v) for k, g, v in _pmc(os.path.join(root, "pmc_" + ctr), ctr) if stem in k]
+            if not rows:
+                break
+            gmax = max(g for g, _ in rows)
+            vals = [v for g, v in rows if g == gmax]
+            per[ctr] = {"launches": len(vals), "kib_avg": sum(vals) / len(vals),
+                        "bytes": sum(vals) / len(vals) * 1024.0 * cal[ctr]["factor"]}
+        if len(per) == 2:
+            out[prec] = {"kernel": stem, "source": src, "source_sha256": source_digest(src),
+                         "counters": per,
+                         "bytes_per_launch": per["FETCH_SIZE"]["bytes"] + per["WRITE_SIZE"]["bytes"]}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out), flush=True)
+
+
+def measured_traffic(path, prec):
+    """Bytes per launch from the --traffic file, or None when absent or when the
+    kernel source has changed since the counters were taken."""
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        ent = json.load(f).get(prec)
+    if not ent or ent.get("source_sha256") != source_digest(ent["source"]):
+        return None
+    return ent["bytes_per_launch"]
 
 
 def log(msg):
@@ -167,14 +239,17 @@ def run(T, w, precision, slices, warmup, steps, field):
 
 def main():
     args = parse()
+    if args.traffic_from:
+        write_traffic(args.traffic_from, args.traffic)
+        return
     if args.copy_probe:
         import torch
-        a = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
+        a = torch.empty(COPY_PROBE_BYTES, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        print(json.dumps({"copy_probe_bytes": COPY_PROBE_BYTES}), flush=True)
         return
     if args.validate:
         validate(args)
@@ -208,9 +283,7 @@ def main():
     if best not in res:
         best = "split"
     r = res[best]
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get(best, {}).get("bytes_per_launch")
+    traffic = measured_traffic(args.traffic, best)
     roof = dict(r["roofline"])
     roof["traffic"] = traffic
     dtype = "f64" if best == "fp64" else f"bf16 (split x{args.slices}, fp32 accumulate, f64 combine)"
