@@ -182,11 +182,23 @@ def cpu_baseline(w, n_steps):
     O.propagate(s, r + 1j * i, n_steps, w.dt, Sinv=Sinv, field=w.field(0, n_steps),
                 record_energy=False)
     el = time.perf_counter() - t0
-    return {"value": n_steps / el, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n_steps} oracle leapfrog steps (charges, potential, H, three "
-                      f"complex128 products, update) at N_orb={s.n_orb} on a seeded Hermitian "
-                      f"density near the neutral rho = 1, numpy/OpenBLAS; S^-1 formed before "
-                      f"timing; {el:.2f} s"}
+    out = {"value": n_steps / el, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{n_steps} oracle leapfrog steps (charges, potential, H, three "
+                     f"complex128 products, update) at N_orb={s.n_orb} on a seeded Hermitian "
+                     f"density near the neutral rho = 1, numpy/OpenBLAS; S^-1 formed before "
+                     f"timing; {el:.2f} s"}
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            O.propagate(s, r + 1j * i, 1, w.dt, Sinv=Sinv, field=w.field(0, 1),
+                        record_energy=False)
+            el1 = time.perf_counter() - t0
+        out["one_thread"] = {"value": 1.0 / el1, "unit": "steps/s", "cores": 1,
+                             "sample": f"1 oracle step, same input; {el1:.2f} s"}
+    except ImportError:
+        pass
+    return out
 
 
 def run(T, w, precision, slices, warmup, steps, field):
@@ -205,6 +217,7 @@ def run(T, w, precision, slices, warmup, steps, field):
     mus.append(p.step(steps, field[warmup:]))     # returns after the stream has drained
     elapsed = time.perf_counter() - t0
     times = {k: p.kernel_time(k) for k in range(4)}
+    charges = p.charges()
     p.close()
     split = precision == T.TD_SPLIT_BF16
     pairs = slices * (slices + 1) // 2
@@ -234,6 +247,7 @@ def run(T, w, precision, slices, warmup, steps, field):
                          "other": times[T.TD_KT_OTHER][0] / max(times[3][1], 1)},
         "fp64_equivalent_tflops": 6.0 * n ** 3 * steps / elapsed / 1e12,
         "dipoles": np.concatenate(mus),
+        "charges": charges,
     }
 
 
@@ -275,6 +289,11 @@ def main():
         ref = res["fp64"]["dipoles"]
         err = float(np.abs(res["split"]["dipoles"] - ref).max() / np.abs(ref - ref[0]).max())
         res["split"]["dipole_rel_err_vs_fp64"] = err
+        # same form for the charges, over the final state (scaled by the largest
+        # charge fluctuation, as no charge series is recorded)
+        dq, dq_ref = res["split"]["charges"], res["fp64"]["charges"]
+        res["split"]["charge_rel_err_vs_fp64"] = float(np.abs(dq - dq_ref).max()
+                                                       / np.abs(dq_ref).max())
         res["split"]["admissible"] = err <= DIPOLE_TOL
     best = "fp64"
     if "split" in res and (res["split"].get("admissible") or "fp64" not in res):
@@ -283,9 +302,11 @@ def main():
     if best not in res:
         best = "split"
     r = res[best]
-    traffic = measured_traffic(args.traffic, best)
+    for k, v in res.items():
+        t = measured_traffic(args.traffic, k)
+        v["roofline"]["traffic"] = t
+        v["hbm_GBps"] = None if t is None else t / (v["roofline"]["avg_launch_ms"] * 1e-3) / 1e9
     roof = dict(r["roofline"])
-    roof["traffic"] = traffic
     dtype = "f64" if best == "fp64" else f"bf16 (split x{args.slices}, fp32 accumulate, f64 combine)"
     out = {
         "metric": "density-matrix steps/s at N_orb=4096 (FP64 vs split-BF16 @1e-6 dipole err)",
@@ -306,7 +327,7 @@ def main():
                    "precision": best, "parallelism": "single GPU"},
         "roofline": roof,
         "trajectory_fs_per_s": r["steps_per_s"] * w.dt * 0.0241888432658,
-        "precisions": {k: {kk: vv for kk, vv in v.items() if kk != "dipoles"}
+        "precisions": {k: {kk: vv for kk, vv in v.items() if kk not in ("dipoles", "charges")}
                        for k, v in res.items()},
     }
     if args.cpu_steps > 0:

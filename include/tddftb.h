@@ -67,10 +67,21 @@ typedef enum {
   TD_SPLIT_BF16 = 1     /* products as split-bf16 slices, fp32 accumulation */
 } td_precision;
 
+/* td_system.flags: the array fields are device pointers (for example the
+ * data of framework tensors) readable on td_options.hip_stream (or the
+ * null stream when that is NULL); td_create reads them once, in stream
+ * order, and keeps no reference. Without the flag they are host pointers. */
+#define TD_DEVICE_PTRS 1u
+
 /* The model: positions, overlap S, non-SCC Hamiltonian H0 (Sec. 2.1,
  * Eq. 6), charge kernel gamma (Sec. 2.1, Eq. 3), reference populations
- * q0, and the electron count (closed shell: n_elec / 2 doubly occupied
- * states). rho0 is optional: NULL asks td_create for the self-consistent
+ * q0, and the occupations of the ground state (Sec. 2.1): either occ,
+ * the occupation of each generalized eigenstate in ascending energy, or,
+ * when occ is NULL, the electron count n_elec (closed shell: n_elec / 2
+ * doubly occupied states). The ground state is found by zero-temperature
+ * purification, so occ must be closed-shell aufbau: 2 for the lowest
+ * states, then 0 (anything else returns TD_ENOTSUP); n_elec is then 0 or
+ * sum(occ). rho0 is optional: NULL asks td_create for the self-consistent
  * ground state; otherwise it is the initial density matrix,
  * [n_orb * n_orb] interleaved complex128, Hermitian. */
 typedef struct {
@@ -82,8 +93,10 @@ typedef struct {
   const double *H0;            /* [n_orb * n_orb] symmetric, hartree            */
   const double *gamma;         /* [n_atoms * n_atoms] symmetric, hartree        */
   const double *q0;            /* [n_atoms] electrons                           */
-  int32_t n_elec;              /* even, 0 < n_elec <= 2 n_orb                   */
+  int32_t n_elec;              /* even, 0 < n_elec <= 2 n_orb (see occ)         */
   const double *rho0;          /* optional, see above                           */
+  const double *occ;           /* optional [n_orb], see above                   */
+  uint32_t flags;              /* 0 or TD_DEVICE_PTRS                           */
 } td_system;
 
 typedef struct {

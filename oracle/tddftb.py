@@ -47,6 +47,7 @@ C_AU = 137.035999084   # speed of light in atomic units
 __all__ = [
     "atom_of_orbital", "mulliken_populations", "charge_fluctuations",
     "external_potential", "scc_hamiltonian", "scc_hamiltonian_fast", "inverse_overlap", "rho_dot", "rho_dot_rows",
+    "rho_dot_reference_split", "renormalise_delta",
     "euler_step", "leapfrog_step", "kick", "dipole", "energy", "electron_count",
     "GroundState", "ground_state", "Trajectory", "propagate",
     "polarizability", "cross_section", "stationarity_residual",
@@ -135,6 +136,32 @@ def rho_dot_rows(rho, H, Sinv, rows):
     a = Sinv[rows, :] @ H
     b = (rho[rows, :] @ H) @ Sinv
     return -1j * (a @ rho - b)
+
+
+def rho_dot_reference_split(delta, rho_ref, H_ref, dH, Sinv):
+    """Eq. 10 (D = 0) written around a fixed reference density and Hamiltonian.
+
+    With rho = rho_ref + delta and H = H_ref + dH, S^-1 H rho expands into
+    S^-1 H_ref rho_ref + (S^-1 H_ref + S^-1 dH) delta + S^-1 dH rho_ref. The
+    first term is fixed for a fixed reference; every other term is of the
+    size of the departure from it. In exact arithmetic this is Eq. 10 itself;
+    it is the form in which reduced-precision products carry only the
+    departure. rhodot = -i (X - X^+), X = S^-1 H rho (S and H symmetric, rho
+    Hermitian, so rho H S^-1 = X^+).
+    """
+    A_ref = Sinv @ H_ref
+    B = Sinv @ dH
+    X = A_ref @ rho_ref + (A_ref + B) @ delta + B @ rho_ref
+    return -1j * (X - X.conj().T)
+
+
+def renormalise_delta(delta, rho_ref, S, n_elec):
+    """Restore Tr(rho S) = N_e (Sec. 2.3: the trace is a constant of the
+    exact motion) by moving rho = rho_ref + delta along rho_ref:
+    delta -= c rho_ref with c = (Tr(rho S) - N_e) / N_e, which needs
+    Tr(rho_ref S) = N_e. A no-op for a density with the exact trace."""
+    c = (electron_count(rho_ref + delta, S) - n_elec) / n_elec
+    return delta - c * rho_ref
 
 
 def euler_step(rho, rhodot, dt):

@@ -325,8 +325,22 @@ void validate(td_ctx* c, const td_system* s, const td_options* o) {
   for (int a = 0; a < s->n_atoms; ++a)
     REQUIRE(c, s->orb_offset[a + 1] > s->orb_offset[a], TD_EINVAL,
             "orb_offset must be strictly increasing");
-  REQUIRE(c, s->n_elec > 0 && s->n_elec % 2 == 0 && s->n_elec <= 2 * s->n_orb, TD_EINVAL,
-          "n_elec must be even and in (0, 2 n_orb]");
+  if (s->occ) {
+    // closed-shell aufbau only: 2 for the lowest states, then 0
+    REQUIRE(c, finite_all(s->occ, (size_t)s->n_orb), TD_EINVAL, "non-finite occ");
+    int n2 = 0;
+    while (n2 < s->n_orb && s->occ[n2] == 2.0) ++n2;
+    bool aufbau = true;
+    for (int i = n2; i < s->n_orb; ++i) aufbau = aufbau && s->occ[i] == 0.0;
+    REQUIRE(c, aufbau, TD_ENOTSUP,
+            "occ must be closed-shell aufbau (2 for the lowest states, then 0): the ground "
+            "state is a zero-temperature purification");
+    REQUIRE(c, s->n_elec == 0 || s->n_elec == 2 * n2, TD_EINVAL, "n_elec must be 0 or sum(occ)");
+    REQUIRE(c, n2 > 0, TD_EINVAL, "occ holds no electrons");
+  } else {
+    REQUIRE(c, s->n_elec > 0 && s->n_elec % 2 == 0 && s->n_elec <= 2 * s->n_orb, TD_EINVAL,
+            "n_elec must be even and in (0, 2 n_orb]");
+  }
   REQUIRE(c, o->dt > 0 && std::isfinite(o->dt), TD_EINVAL, "dt must be positive");
   REQUIRE(c, o->precision == TD_FP64 || o->precision == TD_SPLIT_BF16, TD_EINVAL,
           "unknown precision");
@@ -509,7 +523,61 @@ void upload_padded(td_ctx* c, const double* host, int n, double* dev, int np) {
                              sizeof(double) * n, n, hipMemcpyHostToDevice, c->stream));
 }
 
-void create_impl(td_ctx* c, const td_system* s, const td_options* o) {
+// Host copies of a model given by device pointers.
+struct HostModel {
+  std::vector<int32_t> orb_offset;
+  std::vector<double> positions, S, H0, gamma, q0, rho0, occ;
+};
+
+template <class T>
+void fetch(td_ctx* c, hipStream_t st, const T* src, size_t count, std::vector<T>& dst) {
+  dst.resize(count);
+  if (src)
+    HIPCHK(c, hipMemcpyAsync(dst.data(), src, sizeof(T) * count, hipMemcpyDeviceToHost, st));
+}
+
+// Reads a device-pointer model into host memory (stream order of `st`) and
+// returns a host-pointer view of it.
+td_system host_view(td_ctx* c, const td_system* s, const td_options* o, HostModel& m) {
+  REQUIRE(c, s && o, TD_EINVAL, "null system or options");
+  REQUIRE(c, s->n_atoms > 0 && s->n_orb > 0 && s->n_orb <= 65536 && s->n_atoms <= s->n_orb,
+          TD_EINVAL, "n_atoms and n_orb must be positive, n_atoms <= n_orb <= 65536");
+  REQUIRE(c, s->orb_offset && s->positions && s->S && s->H0 && s->gamma && s->q0, TD_EINVAL,
+          "null array in td_system");
+  hipStream_t st = (hipStream_t)o->hip_stream;
+  const size_t n = (size_t)s->n_orb, na = (size_t)s->n_atoms;
+  fetch(c, st, s->orb_offset, na + 1, m.orb_offset);
+  fetch(c, st, s->positions, 3 * na, m.positions);
+  fetch(c, st, s->S, n * n, m.S);
+  fetch(c, st, s->H0, n * n, m.H0);
+  fetch(c, st, s->gamma, na * na, m.gamma);
+  fetch(c, st, s->q0, na, m.q0);
+  if (s->rho0) fetch(c, st, s->rho0, 2 * n * n, m.rho0);
+  if (s->occ) fetch(c, st, s->occ, n, m.occ);
+  HIPCHK(c, hipStreamSynchronize(st));
+  td_system h = *s;
+  h.orb_offset = m.orb_offset.data();
+  h.positions = m.positions.data();
+  h.S = m.S.data();
+  h.H0 = m.H0.data();
+  h.gamma = m.gamma.data();
+  h.q0 = m.q0.data();
+  h.rho0 = s->rho0 ? m.rho0.data() : nullptr;
+  h.occ = s->occ ? m.occ.data() : nullptr;
+  h.flags = 0;
+  return h;
+}
+
+void create_impl(td_ctx* c, const td_system* s_in, const td_options* o) {
+  REQUIRE(c, s_in && o, TD_EINVAL, "null system or options");
+  REQUIRE(c, (s_in->flags & ~TD_DEVICE_PTRS) == 0, TD_EINVAL, "unknown td_system flags");
+  HostModel staged;
+  td_system view;
+  const td_system* s = s_in;
+  if (s_in->flags & TD_DEVICE_PTRS) {
+    view = host_view(c, s_in, o, staged);
+    s = &view;
+  }
   validate(c, s, o);
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
@@ -524,7 +592,13 @@ void create_impl(td_ctx* c, const td_system* s, const td_options* o) {
   c->ns = o->n_slices;
   // split products accumulate exactly over 256-long K chunks
   c->np = round_up(s->n_orb, want_split ? 256 : td::kPad);
-  c->nelec = s->n_elec;
+  if (s->occ) {
+    int n2 = 0;
+    while (n2 < s->n_orb && s->occ[n2] == 2.0) ++n2;
+    c->nelec = 2 * n2;
+  } else {
+    c->nelec = s->n_elec;
+  }
   const int na = c->na, n = c->n, np = c->np;
   if (o->hip_stream) {
     c->stream = (hipStream_t)o->hip_stream;

@@ -20,6 +20,7 @@ TD_OK, TD_EINVAL, TD_ENOMEM, TD_EHIP, TD_ENOTPOSDEF = 0, -1, -2, -3, -4
 TD_ESCF, TD_EUNSTABLE, TD_ENOTSUP, TD_ESTATE = -5, -6, -7, -8
 TD_FP64, TD_SPLIT_BF16 = 0, 1
 TD_KT_GEMM_SH, TD_KT_GEMM_ARHO, TD_KT_UPDATE, TD_KT_OTHER = 0, 1, 2, 3
+TD_DEVICE_PTRS = 1
 
 EXPORTED = [
     "td_default_options", "td_create", "td_kick", "td_step", "td_get_charges",
@@ -35,7 +36,8 @@ _ip = ctypes.POINTER(ctypes.c_int32)
 class TdSystem(ctypes.Structure):
     _fields_ = [("n_atoms", ctypes.c_int32), ("n_orb", ctypes.c_int32),
                 ("orb_offset", _ip), ("positions", _dp), ("S", _dp), ("H0", _dp),
-                ("gamma", _dp), ("q0", _dp), ("n_elec", ctypes.c_int32), ("rho0", _dp)]
+                ("gamma", _dp), ("q0", _dp), ("n_elec", ctypes.c_int32), ("rho0", _dp),
+                ("occ", _dp), ("flags", ctypes.c_uint32)]
 
 
 class TdOptions(ctypes.Structure):
@@ -135,9 +137,46 @@ class _Keep:
     """Host arrays kept alive while a td_system refers to them."""
 
 
-def td_create(system, options: Optional[TdOptions] = None, rho0: Optional[np.ndarray] = None):
+def _create(s: TdSystem, options: Optional[TdOptions]):
+    opt = options if options is not None else td_default_options()
+    ctx = ctypes.c_void_p()
+    err = ctypes.create_string_buffer(1024)
+    st = load().td_create(ctypes.byref(s), ctypes.byref(opt), ctypes.byref(ctx), err, 1024)
+    if st != TD_OK:
+        raise TdError(st, err.value.decode())
+    return ctx
+
+
+def td_create_from_tensors(orb_offset, positions, S, H0, gamma, q0, n_elec: int = 0,
+                           rho0=None, occ=None, options: Optional[TdOptions] = None):
+    """td_create with TD_DEVICE_PTRS: the arrays are contiguous GPU tensors
+    (int32 orb_offset, float64 arrays, complex128 rho0). Unless options name a
+    stream, the library reads them on, and then uses, the current stream."""
+    import torch
+    arrs = {"orb_offset": (orb_offset, torch.int32), "positions": (positions, torch.float64),
+            "S": (S, torch.float64), "H0": (H0, torch.float64), "gamma": (gamma, torch.float64),
+            "q0": (q0, torch.float64), "rho0": (rho0, torch.complex128),
+            "occ": (occ, torch.float64)}
+    ptrs = {}
+    for name, (t, dt) in arrs.items():
+        if t is None:
+            ptrs[name] = None
+            continue
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {dt} GPU tensor")
+        ptrs[name] = ctypes.cast(ctypes.c_void_p(t.data_ptr()),
+                                 _ip if dt == torch.int32 else _dp)
+    opt = options if options is not None else td_default_options()
+    if not opt.hip_stream:
+        opt.hip_stream = torch.cuda.current_stream().cuda_stream
+    s = TdSystem(n_atoms=int(q0.numel()), n_orb=int(S.shape[0]), n_elec=int(n_elec),
+                 flags=TD_DEVICE_PTRS, **ptrs)
+    return _create(s, opt)
+
+
+def td_create(system, options: Optional[TdOptions] = None, rho0: Optional[np.ndarray] = None,
+              occ: Optional[np.ndarray] = None):
     """td_create: returns an opaque context handle (c_void_p)."""
-    lib = load()
     keep = _Keep()
     keep.off = np.ascontiguousarray(system.orb_offset, dtype=np.int32)
     keep.pos = _f64(system.positions)
@@ -146,17 +185,14 @@ def td_create(system, options: Optional[TdOptions] = None, rho0: Optional[np.nda
     keep.gamma = _f64(system.gamma)
     keep.q0 = _f64(system.q0)
     keep.rho0 = None if rho0 is None else np.ascontiguousarray(rho0, dtype=np.complex128)
+    keep.occ = None if occ is None else _f64(occ)
     s = TdSystem(n_atoms=len(keep.q0), n_orb=int(keep.off[-1]), orb_offset=_ptr(keep.off, np.int32),
                  positions=_ptr(keep.pos), S=_ptr(keep.S), H0=_ptr(keep.H0),
-                 gamma=_ptr(keep.gamma), q0=_ptr(keep.q0), n_elec=int(system.n_elec),
-                 rho0=None if keep.rho0 is None else keep.rho0.ctypes.data_as(_dp))
-    opt = options if options is not None else td_default_options()
-    ctx = ctypes.c_void_p()
-    err = ctypes.create_string_buffer(1024)
-    st = lib.td_create(ctypes.byref(s), ctypes.byref(opt), ctypes.byref(ctx), err, 1024)
-    if st != TD_OK:
-        raise TdError(st, err.value.decode())
-    return ctx
+                 gamma=_ptr(keep.gamma), q0=_ptr(keep.q0),
+                 n_elec=int(system.n_elec) if occ is None else 0,
+                 rho0=None if keep.rho0 is None else keep.rho0.ctypes.data_as(_dp),
+                 occ=_ptr(keep.occ), flags=0)
+    return _create(s, options)
 
 
 def _check(ctx, st):
@@ -271,7 +307,8 @@ def td_util_gemm(A: np.ndarray, B: np.ndarray, precision: int = TD_FP64,
 class Propagator:
     """Convenience wrapper owning one context (one trajectory)."""
 
-    def __init__(self, system, dt=0.2, precision=TD_FP64, n_slices=4, rho0=None, profile=False,
+    def __init__(self, system, dt=0.2, precision=TD_FP64, n_slices=4, rho0=None, occ=None,
+                 profile=False,
                  scc_tol=1e-12, scc_maxiter=300):
         opt = td_default_options()
         opt.dt = dt
@@ -282,7 +319,7 @@ class Propagator:
         opt.scc_maxiter = scc_maxiter
         self.n_atoms = len(system.q0)
         self.n_orb = int(system.orb_offset[-1])
-        self.ctx = td_create(system, opt, rho0=rho0)
+        self.ctx = td_create(system, opt, rho0=rho0, occ=occ)
 
     def kick(self, e0, direction):
         td_kick(self.ctx, e0, direction)

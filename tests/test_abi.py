@@ -71,7 +71,25 @@ def test_invalid_arguments_rejected_before_device(T):
     with pytest.raises(T.TdError) as e:
         T.td_create(s, o)
     assert e.value.status == T.TD_EINVAL
+    occ = np.zeros(s.n_orb)
+    occ[: s.n_elec // 2] = 2.0
+    frac = occ.copy()
+    frac[s.n_elec // 2 - 1 : s.n_elec // 2 + 1] = 1.0      # open shell: not a purification
+    with pytest.raises(T.TdError) as e:
+        T.td_create(s, occ=frac)
+    assert e.value.status == T.TD_ENOTSUP
+    holes = occ.copy()
+    holes[0], holes[s.n_elec // 2] = 0.0, 2.0               # not aufbau
+    with pytest.raises(T.TdError) as e:
+        T.td_create(s, occ=holes)
+    assert e.value.status == T.TD_ENOTSUP
     lib = T.load()
+    sysd = T.TdSystem(n_atoms=1, n_orb=1, flags=2)          # unknown flag
+    err = ctypes.create_string_buffer(256)
+    ctx = ctypes.c_void_p()
+    assert lib.td_create(ctypes.byref(sysd), ctypes.byref(o), ctypes.byref(ctx), err, 256) \
+        == T.TD_EINVAL
+    assert b"flags" in err.value
     assert lib.td_kick(None, 1e-3, None) == T.TD_EINVAL
     assert lib.td_step(None, 1, None) == T.TD_EINVAL
 

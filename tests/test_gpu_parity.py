@@ -204,6 +204,39 @@ def test_repeat_runs_are_bitwise_identical(flake):
     assert np.array_equal(out[0], out[1])
 
 
+def test_occupations_and_device_tensors_give_the_same_run(flake):
+    """occ (aufbau) instead of n_elec, and the model handed over as GPU tensors
+    (TD_DEVICE_PTRS), reproduce the host-array run bit for bit."""
+    import torch
+    T = _T()
+    s, gs, _ = flake
+    say("occ and device tensors")
+    runs = []
+    p = T.Propagator(s, scc_tol=1e-13)
+    p.kick(1e-3, (0.0, 1.0, 0.0))
+    runs.append(p.step(60))
+    p.close()
+    occ = np.zeros(s.n_orb)
+    occ[: s.n_elec // 2] = 2.0
+    p = T.Propagator(s, occ=occ, scc_tol=1e-13)
+    p.kick(1e-3, (0.0, 1.0, 0.0))
+    runs.append(p.step(60))
+    p.close()
+    dev = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).cuda()
+    opt = T.td_default_options()
+    opt.scc_tol = 1e-13
+    ctx = T.td_create_from_tensors(dev(s.orb_offset, torch.int32), dev(s.positions), dev(s.S),
+                                   dev(s.H0), dev(s.gamma), dev(s.q0), n_elec=s.n_elec,
+                                   options=opt)
+    T.td_kick(ctx, 1e-3, (0.0, 1.0, 0.0))
+    T.td_step(ctx, 60)
+    runs.append(T.td_get_dipole_series(ctx, 60))
+    T.td_destroy(ctx)
+    torch.cuda.synchronize()
+    assert np.array_equal(runs[0], runs[1])
+    assert np.array_equal(runs[0], runs[2])
+
+
 def test_electron_count_and_hermiticity_on_gpu(flake):
     T = _T()
     s, gs, Sinv = flake

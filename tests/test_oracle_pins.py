@@ -376,3 +376,43 @@ def test_row_sampled_rhodot_equals_full(flake, flake_gs):
     rows = [0, 7, 50, s.n_orb - 1]
     full = O.rho_dot(rk, H, Sinv)
     assert np.abs(O.rho_dot_rows(rk, H, Sinv, rows) - full[rows]).max() < 1e-14
+
+
+def test_reference_split_form_equals_eq10(flake, flake_gs):
+    """The reference-density form of Eq. 10 equals the direct form (pinned above)
+    for a kicked SCC state in a field, and its reference part alone vanishes at
+    the stationary ground state."""
+    s = flake
+    Sinv = O.inverse_overlap(s.S)
+    rho_ref = flake_gs.rho
+    H_ref = O.scc_hamiltonian_fast(s.H0, s.S, s.gamma, flake_gs.dq, s.orb_offset)
+    rk = O.kick(rho_ref, s.S, Sinv, s.positions, s.orb_offset, 1e-2, (1.0, 0.5, 0.0))
+    tr = O.propagate(s, rk, 30, 0.2, Sinv=Sinv, record_energy=False,
+                     field=np.tile([0.0, 0.003, 0.0], (30, 1)))
+    rho = tr.rho
+    dq = O.charge_fluctuations(rho, s.S, s.orb_offset, s.q0)
+    H = O.scc_hamiltonian_fast(s.H0, s.S, s.gamma, dq, s.orb_offset,
+                               O.external_potential(s.positions, [0.0, 0.003, 0.0]))
+    direct = O.rho_dot(rho, H, Sinv)
+    split = O.rho_dot_reference_split(rho - rho_ref, rho_ref, H_ref, H - H_ref, Sinv)
+    assert np.abs(split - direct).max() < 1e-13 * np.abs(direct).max() + 1e-15
+    assert np.abs(direct).max() > 1e-4
+    zero = np.zeros_like(rho)
+    still = O.rho_dot_reference_split(zero, rho_ref, H_ref, np.zeros_like(H_ref), Sinv)
+    assert np.abs(still).max() < 1e-10
+
+
+def test_trace_renormalisation(flake, flake_gs):
+    """Moving along rho_ref restores Tr(rho S) = N_e exactly and is a no-op on
+    a density that already has it (leapfrog keeps the trace, Sec. 2.3)."""
+    s = flake
+    Sinv = O.inverse_overlap(s.S)
+    rho_ref = flake_gs.rho
+    rk = O.kick(rho_ref, s.S, Sinv, s.positions, s.orb_offset, 1e-2, (0.0, 1.0, 0.0))
+    delta = rk - rho_ref
+    same = O.renormalise_delta(delta, rho_ref, s.S, s.n_elec)
+    assert np.abs(same - delta).max() < 1e-15
+    off = delta + 1e-3 * rho_ref                  # trace off by 1e-3 N_e
+    fixed = O.renormalise_delta(off, rho_ref, s.S, s.n_elec)
+    assert abs(O.electron_count(rho_ref + fixed, s.S) - s.n_elec) < 1e-12
+    assert np.abs(fixed - delta).max() < 1e-14
