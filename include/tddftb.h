@@ -213,6 +213,63 @@ TD_API td_status td_util_gemm(int32_t precision, int32_t n_slices, int32_t m, in
                               int32_t k, const double *A, const double *B, double *C,
                               char *err, int32_t errlen);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent trajectories of different sizes stepped together, as in
+ * the pump-probe protocol (Sec. 5.1: one probe trajectory per pump delay,
+ * phase and kick direction, each a clamped-nuclei propagation of its own
+ * density matrix). Every member follows exactly the trajectory a solo
+ * context created from the same td_system would follow (bitwise, FP64);
+ * each kernel of a step covers all members in one launch, and the steps
+ * after the first are replayed from a captured HIP graph. */
+typedef struct td_batch td_batch;
+
+#define TD_BATCH_NO_GRAPH 1u   /* launch each step's kernels directly            */
+#define TD_BATCH_TILE_128 2u   /* no tuning: 128 x 128 product tiles everywhere  */
+#define TD_BATCH_TILE_64 4u    /* no tuning: 64 x 64 product tiles everywhere    */
+
+#define TD_BATCH_BUCKETS 8     /* size buckets: padded n / 128 - 1, capped at 7  */
+
+typedef struct {
+  int32_t n_members;
+  int64_t step;                          /* index of the current densities       */
+  int32_t has_prev;
+  int32_t graph;                         /* 1: steps replay a captured graph     */
+  int32_t bucket_members[TD_BATCH_BUCKETS];
+  int32_t bucket_tile[TD_BATCH_BUCKETS]; /* product tile edge used per bucket    */
+  double bucket_ms[TD_BATCH_BUCKETS][2]; /* tuning: ms per launch, 128 and 64    */
+} td_batch_info;
+
+/* Creates a batch of n >= 1 trajectories, systems[m] as for td_create
+ * (host or device pointers per its flags; rho0 NULL: SCC ground state).
+ * opt applies to every member and must ask for TD_FP64 (split-bf16
+ * batches return TD_ENOTSUP). flags: TD_BATCH_* bits. Without a TILE flag
+ * the library times both product tiles on each size bucket's members and
+ * keeps the faster one. The batch owns one stream (opt.hip_stream, or its
+ * own); a failure names the member in err. */
+TD_API td_status td_batch_create(int32_t n, const td_system *systems, const td_options *opt,
+                                 uint32_t flags, td_batch **out, char *err, int32_t errlen);
+
+/* Kicks member m with e0[m] along dir[3m..3m+2] (Sec. 2.2, Eq. 16;
+ * e0[m] = 0 leaves it unkicked but still restarts its integrator, as all
+ * members share one step counter). Next step is an Euler start. */
+TD_API td_status td_batch_kick(td_batch *b, const double *e0, const double *dir);
+
+/* Advances every member n >= 0 steps (Sec. 2.3, Eq. 19); field is NULL or
+ * [n * 3], the same field for all members. Records each member's dipole of
+ * each density entering a step. TD_EUNSTABLE names the first non-finite
+ * member. */
+TD_API td_status td_batch_step(td_batch *b, int32_t n, const double *field);
+
+/* Per-member results, as the td_get_* calls of a solo context. */
+TD_API td_status td_batch_get_dipole_series(td_batch *b, int32_t member, double *mu, int32_t cap,
+                                            int32_t *n_out);
+TD_API td_status td_batch_get_charges(td_batch *b, int32_t member, double *dq);
+TD_API td_status td_batch_get_rho(td_batch *b, int32_t member, double *rho, double *rho_prev,
+                                  int64_t *step, int32_t *has_prev);
+TD_API td_status td_batch_get_info(td_batch *b, td_batch_info *info);
+TD_API const char *td_batch_last_error(const td_batch *b);
+TD_API void td_batch_destroy(td_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtddftb.so")
-SOURCES = ["gemm_f64.hip", "gemm_split_bf16.hip", "kernels.hip", "tddftb.hip"]
+SOURCES = ["gemm_f64.hip", "gemm_split_bf16.hip", "kernels.hip", "batch_kernels.hip", "tddftb.hip",
+           "batch.hip"]
 ARCH = "gfx950"
 
 

@@ -27,6 +27,72 @@ hipError_t dgemm(hipStream_t s, int tag, int m, int n, int k, double alpha,
                  const double* A, int lda, const double* B, int ldb, double beta,
                  const double* Cin, int ldcin, double* C, int ldc);
 
+// One product of a grouped launch: C = A B with A [m x K], B [K x n] and
+// m, n multiples of the launch's tile, K a multiple of 16. tile0 is the
+// index of the problem's first tile in the launch (problems in ascending
+// tile0, tile0 of the first = 0).
+struct GemmProblem {
+  const double* A;
+  const double* B;
+  double* C;
+  int lda, ldb, ldc, K;
+  int tiles_m, tiles_n, tile0, pad_;
+};
+
+// All problems of `probs` (device array, nprob entries, ntiles tiles in
+// total) in one launch with tile x tile macro tiles (tile = 128 or 64).
+// Every output element is accumulated in the same order as by dgemm, so
+// both give bitwise identical results.
+hipError_t dgemm_grouped(hipStream_t s, int tile, const GemmProblem* probs, int nprob,
+                         int ntiles);
+
+// ---------------------------------------------------------------- batches
+// Device buffers of one trajectory of a batch (layouts as for one
+// trajectory: np x np real, np x 2np wide planar complex).
+struct BatchMember {
+  const double* S;
+  const double* H0;
+  double* H;
+  double* A;
+  double* X;
+  double* R[2];          // the two density buffers
+  const double* gamma;
+  const double* pos;
+  const double* q0;
+  const int* orb_off;
+  double* q_orb;
+  double* dq;
+  double* v;
+  double* vorb;
+  int np, na;
+};
+struct BatchItem {        // row (or atom) r of member m
+  int m, r;
+};
+struct BatchPair {        // 32 x 32 tiles (bi, bj) and (bj, bi) of member m, bi <= bj
+  int m, bi, bj, pad_;
+};
+
+// The step kernels of one trajectory applied to every member of a batch in
+// one launch each, with the same arithmetic in the same order (bitwise equal
+// to the one-trajectory kernels). `cur` / `base` / `out` index R[].
+// q_orb[r] = sum_c Re R[cur][r, c] S[r, c] for each listed row.
+hipError_t batch_rowdot(hipStream_t s, const BatchMember* mem, const BatchItem* rows, int nrows,
+                        int cur);
+// dq and the dipole of each member; dipole -> dip[(m * cap + *kstep) * 3].
+hipError_t batch_charges(hipStream_t s, const BatchMember* mem, int nm, const int* kstep,
+                         double* dip, int cap);
+// v and vorb of each listed atom with the field field[3 * *kstep].
+hipError_t batch_potential(hipStream_t s, const BatchMember* mem, const BatchItem* atoms,
+                           int natoms, const double* field, const int* kstep);
+// H rows of each listed row.
+hipError_t batch_assemble(hipStream_t s, const BatchMember* mem, const BatchItem* rows, int nrows);
+// R[out] = R[base] + f rhodot(X) on each listed tile pair.
+hipError_t batch_leapfrog(hipStream_t s, const BatchMember* mem, const BatchPair* pairs, int npairs,
+                          int base, int out, double f);
+// *kstep += 1, or = 0 (plain kernels, so they can be captured in a graph).
+hipError_t batch_tick(hipStream_t s, int* kstep, int reset);
+
 // ---------------------------------------------------------------- O(n^2) kernels
 // out[r] = sum_c X[r, c] * Y[r, c] for r < rows (cols multiple of 2).
 hipError_t rowdot(hipStream_t s, const double* X, int ldx, const double* Y, int ldy,

@@ -1,0 +1,113 @@
+// Private state of the TD-DFTB library shared by its host sources: the
+// per-trajectory context behind the opaque td_ctx handle, and the error
+// plumbing of the C entry points (no exception crosses the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tddftb.h"
+
+struct td_ctx {
+  int na = 0, n = 0, np = 0, nelec = 0;
+  td_options opt{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  double *S = nullptr, *H0 = nullptr, *Sinv = nullptr, *H = nullptr, *A = nullptr;
+  double *rho_cur = nullptr, *rho_prev = nullptr, *X = nullptr;
+  double *gamma = nullptr, *pos = nullptr, *q0 = nullptr;
+  int* orb_off = nullptr;
+  double *q_orb = nullptr, *dq = nullptr, *dq_in = nullptr, *v = nullptr, *vorb = nullptr;
+  double *xorb = nullptr, *work1 = nullptr, *work2 = nullptr, *scal = nullptr;
+  double *hx = nullptr, *hf = nullptr;
+  double* field = nullptr;
+  int field_cap = 0;
+  double* dip = nullptr;
+  int dip_cap = 0;
+  std::vector<int> orb_off_h;
+  std::vector<double> pos_h;
+  std::vector<double> dq_h;
+  double mu_h[3] = {0, 0, 0};
+  int64_t step = 0;
+  bool has_prev = false;
+  int last_n = 0;
+  td_info info{};
+  std::string err;
+  // split-bf16 precision: the state buffers hold rho - rho_ref
+  bool split = false;
+  int ns = 4;
+  double *rho_ref = nullptr;   // np x np real reference density (the initial state)
+  double *Agsb = nullptr;      // S^-1 H_ref
+  double *Xref = nullptr;      // np x 2np wide: (S^-1 H_ref) rho_ref | 0
+  double *q_ref = nullptr;     // np: Mulliken row sums of rho_ref
+  double *v_ref = nullptr;     // na: SCC potential of rho_ref
+  double *band_ref = nullptr;  // np: row sums of rho_ref o H0
+  double *stage = nullptr;     // np x 2np scratch
+  __bf16 *sl_sinv = nullptr, *sl_dh = nullptr, *sl_L2 = nullptr, *sl_R2 = nullptr;
+  int *e_sinv = nullptr, *e_dh = nullptr, *e_L2 = nullptr, *e_R2 = nullptr;
+  // profiling
+  std::vector<hipEvent_t> ev;
+  double kt_ms[TD_KT_COUNT] = {0, 0, 0, 0};
+  int64_t kt_n[TD_KT_COUNT] = {0, 0, 0, 0};
+};
+
+namespace tdi {
+
+struct Fail {
+  td_status st;
+};
+
+inline void set_err(char* buf, int len, const std::string& m) {
+  if (buf && len > 0) {
+    std::snprintf(buf, (size_t)len, "%s", m.c_str());
+  }
+}
+
+#define HIPCHK(ctx, expr)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);                       \
+      throw tdi::Fail{e_ == hipErrorOutOfMemory ? TD_ENOMEM : TD_EHIP};                     \
+    }                                                                                       \
+  } while (0)
+
+#define REQUIRE(ctx, cond, status, msg) \
+  do {                                  \
+    if (!(cond)) {                      \
+      (ctx)->err = (msg);               \
+      throw tdi::Fail{status};          \
+    }                                   \
+  } while (0)
+
+// Runs f, mapping failures to a status; C is any context with an `err` string.
+template <class C, class F>
+td_status guarded(C* ctx, F&& f) {
+  if (!ctx) return TD_EINVAL;
+  try {
+    ctx->err.clear();
+    f();
+    return TD_OK;
+  } catch (const Fail& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "host allocation failed";
+    return TD_ENOMEM;
+  } catch (...) {
+    ctx->err = "unexpected internal error";
+    return TD_EHIP;
+  }
+}
+
+// Waits for the context's stream.
+void sync_ctx(td_ctx* c);
+// Mulliken charges and dipole of the current density copied to the host
+// (what td_get_charges / td_get_dipole return); checks finiteness.
+void refresh_ctx(td_ctx* c);
+
+}  // namespace tdi

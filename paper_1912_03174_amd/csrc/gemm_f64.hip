@@ -162,7 +162,153 @@ __global__ __launch_bounds__(256) void dgemm_nn(const double* __restrict__ A, in
   }
 }
 
+// Grouped form: the block id picks a problem (binary search over tile0)
+// and a tile inside it. BT = 128: the same waves, LDS staging and MFMA
+// sequence as dgemm_nn; BT = 64: four waves of 32 x 32 (2 x 2 MFMA blocks
+// each) for small matrices, where 128-wide tiles would mostly multiply
+// padding. Each output element sees the same MFMA sequence over k in both.
+template <int BT>
+__global__ __launch_bounds__(256) void dgemm_grouped_k(const GemmProblem* __restrict__ probs,
+                                                       int nprob, int ntiles) {
+  constexpr int FR = BT / 32;                 // 16 x 16 blocks per wave dimension
+  constexpr int EA = BT * BK / 256;           // A (and B) elements loaded per thread: 8 or 4
+  constexpr int EB = EA;
+  constexpr int LD = BT + PAD;
+  __shared__ double As[2][BK][LD];
+  __shared__ double Bs[2][BK][LD];
+
+  // XCD-aware order over the launch's tiles (a problem's tiles stay together).
+  const int w = blockIdx.x;
+  const int q = ntiles >> 3, r = ntiles & 7;
+  const int xcd = w & 7, slot = w >> 3;
+  const int lin = xcd * q + (xcd < r ? xcd : r) + slot;
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (probs[mid].tile0 <= lin) lo = mid; else hi = mid - 1;
+  }
+  const GemmProblem* pp = probs + lo;
+  const int tiles_m = pp->tiles_m, tiles_n = pp->tiles_n;
+  const int lda = pp->lda, ldb = pp->ldb, ldc = pp->ldc, Kp = pp->K;
+  const double* __restrict__ Ap = pp->A;
+  const double* __restrict__ Bp = pp->B;
+  double* Cp = pp->C;
+  const int local = lin - pp->tile0;
+  const int group = GROUP_M * tiles_n;
+  const int g = local / group;
+  const int first_m = g * GROUP_M;
+  const int gsz = (tiles_m - first_m) < GROUP_M ? (tiles_m - first_m) : GROUP_M;
+  const int in_g = local - g * group;
+  const int m0 = (first_m + in_g % gsz) * BT, n0 = (in_g / gsz) * BT;
+
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+
+  constexpr int APR = BK / EA;                // threads per A row
+  constexpr int BPR = BT / EB;                // threads per B k row
+  const int a_row = t / APR, a_k = (t % APR) * EA;
+  const int b_k = t / BPR, b_n = (t % BPR) * EB;
+  const double* Ag = Ap + (size_t)(m0 + a_row) * lda + a_k;
+  const double* Bg = Bp + (size_t)b_k * ldb + n0 + b_n;
+
+  d4 acc[FR][FR];
+#pragma unroll
+  for (int i = 0; i < FR; ++i)
+#pragma unroll
+    for (int j = 0; j < FR; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  // staging registers (named, so they stay in VGPRs); ra2/3, rb2/3 unused for BT = 64
+  double2 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+#define TD_G_LOAD(kt)                                                          \
+  do {                                                                         \
+    const double* an_ = Ag + (size_t)(kt) * BK;                                \
+    const double* bn_ = Bg + (size_t)(kt) * BK * ldb;                          \
+    ra0 = *reinterpret_cast<const double2*>(an_ + 0);                          \
+    ra1 = *reinterpret_cast<const double2*>(an_ + 2);                          \
+    rb0 = *reinterpret_cast<const double2*>(bn_ + 0);                          \
+    rb1 = *reinterpret_cast<const double2*>(bn_ + 2);                          \
+    if constexpr (EA == 8) {                                                   \
+      ra2 = *reinterpret_cast<const double2*>(an_ + 4);                        \
+      ra3 = *reinterpret_cast<const double2*>(an_ + 6);                        \
+      rb2 = *reinterpret_cast<const double2*>(bn_ + 4);                        \
+      rb3 = *reinterpret_cast<const double2*>(bn_ + 6);                        \
+    }                                                                          \
+  } while (0)
+#define TD_G_STORE(buf)                                                        \
+  do {                                                                         \
+    As[buf][a_k + 0][a_row] = ra0.x;                                           \
+    As[buf][a_k + 1][a_row] = ra0.y;                                           \
+    As[buf][a_k + 2][a_row] = ra1.x;                                           \
+    As[buf][a_k + 3][a_row] = ra1.y;                                           \
+    *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n + 0]) = rb0;                 \
+    *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n + 2]) = rb1;                 \
+    if constexpr (EA == 8) {                                                   \
+      As[buf][a_k + 4][a_row] = ra2.x;                                         \
+      As[buf][a_k + 5][a_row] = ra2.y;                                         \
+      As[buf][a_k + 6][a_row] = ra3.x;                                         \
+      As[buf][a_k + 7][a_row] = ra3.y;                                         \
+      *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n + 4]) = rb2;               \
+      *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n + 6]) = rb3;               \
+    }                                                                          \
+  } while (0)
+
+  const int nk = Kp / BK;
+  TD_G_LOAD(0);
+  TD_G_STORE(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) TD_G_LOAD(kt + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kl = kk + lk;
+      double a[FR], b[FR];
+#pragma unroll
+      for (int i = 0; i < FR; ++i) a[i] = As[cur][kl][wm * (BT / 2) + i * 16 + l16];
+#pragma unroll
+      for (int j = 0; j < FR; ++j) b[j] = Bs[cur][kl][wn * (BT / 2) + j * 16 + l16];
+#pragma unroll
+      for (int i = 0; i < FR; ++i)
+#pragma unroll
+        for (int j = 0; j < FR; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) TD_G_STORE(cur ^ 1);
+    __syncthreads();
+  }
+#undef TD_G_LOAD
+#undef TD_G_STORE
+
+#pragma unroll
+  for (int i = 0; i < FR; ++i)
+#pragma unroll
+    for (int j = 0; j < FR; ++j) {
+      const int col = n0 + wn * (BT / 2) + j * 16 + l16;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int row = m0 + wm * (BT / 2) + i * 16 + lk + 4 * rr;
+        Cp[(size_t)row * ldc + col] = 1.0 * acc[i][j][rr];
+      }
+    }
+}
+
 }  // namespace
+
+hipError_t dgemm_grouped(hipStream_t s, int tile, const GemmProblem* probs, int nprob,
+                         int ntiles) {
+  if (nprob <= 0 || ntiles <= 0 || !probs) return hipErrorInvalidValue;
+  if (tile == 128)
+    hipLaunchKernelGGL(dgemm_grouped_k<128>, dim3(ntiles), dim3(256), 0, s, probs, nprob, ntiles);
+  else if (tile == 64)
+    hipLaunchKernelGGL(dgemm_grouped_k<64>, dim3(ntiles), dim3(256), 0, s, probs, nprob, ntiles);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
 
 hipError_t dgemm(hipStream_t s, int tag, int m, int n, int k, double alpha, const double* A,
                  int lda, const double* B, int ldb, double beta, const double* Cin, int ldcin,

@@ -21,52 +21,10 @@
 
 #include "../../include/tddftb.h"
 #include "common.hpp"
+#include "ctx.hpp"
 #include "split.hpp"
 
 using td::round_up;
-
-struct td_ctx {
-  int na = 0, n = 0, np = 0, nelec = 0;
-  td_options opt{};
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  double *S = nullptr, *H0 = nullptr, *Sinv = nullptr, *H = nullptr, *A = nullptr;
-  double *rho_cur = nullptr, *rho_prev = nullptr, *X = nullptr;
-  double *gamma = nullptr, *pos = nullptr, *q0 = nullptr;
-  int* orb_off = nullptr;
-  double *q_orb = nullptr, *dq = nullptr, *dq_in = nullptr, *v = nullptr, *vorb = nullptr;
-  double *xorb = nullptr, *work1 = nullptr, *work2 = nullptr, *scal = nullptr;
-  double *hx = nullptr, *hf = nullptr;
-  double* field = nullptr;
-  int field_cap = 0;
-  double* dip = nullptr;
-  int dip_cap = 0;
-  std::vector<int> orb_off_h;
-  std::vector<double> pos_h;
-  std::vector<double> dq_h;
-  double mu_h[3] = {0, 0, 0};
-  int64_t step = 0;
-  bool has_prev = false;
-  int last_n = 0;
-  td_info info{};
-  std::string err;
-  // split-bf16 precision: the state buffers hold rho - rho_ref
-  bool split = false;
-  int ns = 4;
-  double *rho_ref = nullptr;   // np x np real reference density (the initial state)
-  double *Agsb = nullptr;      // S^-1 H_ref
-  double *Xref = nullptr;      // np x 2np wide: (S^-1 H_ref) rho_ref | 0
-  double *q_ref = nullptr;     // np: Mulliken row sums of rho_ref
-  double *v_ref = nullptr;     // na: SCC potential of rho_ref
-  double *band_ref = nullptr;  // np: row sums of rho_ref o H0
-  double *stage = nullptr;     // np x 2np scratch
-  __bf16 *sl_sinv = nullptr, *sl_dh = nullptr, *sl_L2 = nullptr, *sl_R2 = nullptr;
-  int *e_sinv = nullptr, *e_dh = nullptr, *e_L2 = nullptr, *e_R2 = nullptr;
-  // profiling
-  std::vector<hipEvent_t> ev;
-  double kt_ms[TD_KT_COUNT] = {0, 0, 0, 0};
-  int64_t kt_n[TD_KT_COUNT] = {0, 0, 0, 0};
-};
 
 namespace {
 
@@ -74,50 +32,9 @@ namespace {
 enum { SC_MU = 0, SC_NE = 3, SC_RES = 4, SC_TR1 = 5, SC_TR2 = 6, SC_BOUNDS = 8, SC_E = 10,
        SC_RENORM = 13, SC_FIELD = 16, SC_COUNT = 32 };
 
-struct Fail {
-  td_status st;
-};
-
-void set_err(char* buf, int len, const std::string& m) {
-  if (buf && len > 0) {
-    std::snprintf(buf, (size_t)len, "%s", m.c_str());
-  }
-}
-
-#define HIPCHK(ctx, expr)                                                                   \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess) {                                                                 \
-      (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);                       \
-      throw Fail{e_ == hipErrorOutOfMemory ? TD_ENOMEM : TD_EHIP};                          \
-    }                                                                                       \
-  } while (0)
-
-#define REQUIRE(ctx, cond, status, msg) \
-  do {                                  \
-    if (!(cond)) {                      \
-      (ctx)->err = (msg);               \
-      throw Fail{status};               \
-    }                                   \
-  } while (0)
-
-template <class F>
-td_status guarded(td_ctx* ctx, F&& f) {
-  if (!ctx) return TD_EINVAL;
-  try {
-    ctx->err.clear();
-    f();
-    return TD_OK;
-  } catch (const Fail& e) {
-    return e.st;
-  } catch (const std::bad_alloc&) {
-    ctx->err = "host allocation failed";
-    return TD_ENOMEM;
-  } catch (...) {
-    ctx->err = "unexpected internal error";
-    return TD_EHIP;
-  }
-}
+using tdi::Fail;
+using tdi::guarded;
+using tdi::set_err;
 
 void dalloc(td_ctx* c, double** p, size_t count) {
   HIPCHK(c, hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(double)));
@@ -828,6 +745,11 @@ void split_gemm_host(td_ctx* c, int ns, int m, int n, int k, const double* A, co
 }
 
 }  // namespace
+
+namespace tdi {
+void sync_ctx(td_ctx* c) { sync(c); }
+void refresh_ctx(td_ctx* c) { refresh(c); }
+}  // namespace tdi
 
 extern "C" {
 

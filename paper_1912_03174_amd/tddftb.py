@@ -27,7 +27,12 @@ EXPORTED = [
     "td_get_dipole", "td_get_dipole_series", "td_get_energy", "td_get_rho", "td_set_rho",
     "td_get_info", "td_get_kernel_time", "td_reset_kernel_time", "td_get_forces",
     "td_last_error", "td_status_string", "td_destroy", "td_util_gemm",
+    "td_batch_create", "td_batch_kick", "td_batch_step", "td_batch_get_dipole_series",
+    "td_batch_get_charges", "td_batch_get_rho", "td_batch_get_info", "td_batch_last_error",
+    "td_batch_destroy",
 ]
+TD_BATCH_NO_GRAPH, TD_BATCH_TILE_128, TD_BATCH_TILE_64 = 1, 2, 4
+TD_BATCH_BUCKETS = 8
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -103,6 +108,20 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "td_util_gemm": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp,
                                           ctypes.c_char_p, ctypes.c_int32]),
+        "td_batch_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(TdSystem),
+                                             ctypes.POINTER(TdOptions), ctypes.c_uint32,
+                                             ctypes.POINTER(vp), ctypes.c_char_p,
+                                             ctypes.c_int32]),
+        "td_batch_kick": (ctypes.c_int32, [vp, _dp, _dp]),
+        "td_batch_step": (ctypes.c_int32, [vp, ctypes.c_int32, _dp]),
+        "td_batch_get_dipole_series": (ctypes.c_int32, [vp, ctypes.c_int32, _dp, ctypes.c_int32,
+                                                        _ip]),
+        "td_batch_get_charges": (ctypes.c_int32, [vp, ctypes.c_int32, _dp]),
+        "td_batch_get_rho": (ctypes.c_int32, [vp, ctypes.c_int32, _dp, _dp,
+                                              ctypes.POINTER(ctypes.c_int64), _ip]),
+        "td_batch_get_info": (ctypes.c_int32, [vp, ctypes.POINTER(TdBatchInfo)]),
+        "td_batch_last_error": (ctypes.c_char_p, [vp]),
+        "td_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -131,6 +150,20 @@ def td_default_options() -> TdOptions:
     o = TdOptions()
     load().td_default_options(ctypes.byref(o))
     return o
+
+
+class TdBatchInfo(ctypes.Structure):
+    _fields_ = [("n_members", ctypes.c_int32), ("step", ctypes.c_int64),
+                ("has_prev", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("bucket_members", ctypes.c_int32 * TD_BATCH_BUCKETS),
+                ("bucket_tile", ctypes.c_int32 * TD_BATCH_BUCKETS),
+                ("bucket_ms", (ctypes.c_double * 2) * TD_BATCH_BUCKETS)]
+
+    def as_dict(self):
+        return {"n_members": self.n_members, "step": self.step, "has_prev": bool(self.has_prev),
+                "graph": bool(self.graph), "bucket_members": list(self.bucket_members),
+                "bucket_tile": list(self.bucket_tile),
+                "bucket_ms": [list(x) for x in self.bucket_ms]}
 
 
 class _Keep:
@@ -174,9 +207,8 @@ def td_create_from_tensors(orb_offset, positions, S, H0, gamma, q0, n_elec: int 
     return _create(s, opt)
 
 
-def td_create(system, options: Optional[TdOptions] = None, rho0: Optional[np.ndarray] = None,
-              occ: Optional[np.ndarray] = None):
-    """td_create: returns an opaque context handle (c_void_p)."""
+def _host_system(system, rho0=None, occ=None):
+    """TdSystem over host copies of `system`'s arrays (kept alive in the result's _keep)."""
     keep = _Keep()
     keep.off = np.ascontiguousarray(system.orb_offset, dtype=np.int32)
     keep.pos = _f64(system.positions)
@@ -192,7 +224,85 @@ def td_create(system, options: Optional[TdOptions] = None, rho0: Optional[np.nda
                  n_elec=int(system.n_elec) if occ is None else 0,
                  rho0=None if keep.rho0 is None else keep.rho0.ctypes.data_as(_dp),
                  occ=_ptr(keep.occ), flags=0)
-    return _create(s, options)
+    s._keep = keep
+    return s
+
+
+def td_create(system, options: Optional[TdOptions] = None, rho0: Optional[np.ndarray] = None,
+              occ: Optional[np.ndarray] = None):
+    """td_create: returns an opaque context handle (c_void_p)."""
+    return _create(_host_system(system, rho0, occ), options)
+
+
+def _bcheck(b, st):
+    if st != TD_OK:
+        raise TdError(st, load().td_batch_last_error(b).decode())
+
+
+def td_batch_create(systems, options: Optional[TdOptions] = None, rho0s=None, flags: int = 0):
+    """td_batch_create over host arrays; rho0s: None or a list (entries may be None)."""
+    n = len(systems)
+    rho0s = rho0s if rho0s is not None else [None] * n
+    hs = [_host_system(s, r) for s, r in zip(systems, rho0s)]
+    arr = (TdSystem * n)(*hs)
+    opt = options if options is not None else td_default_options()
+    b = ctypes.c_void_p()
+    err = ctypes.create_string_buffer(1024)
+    st = load().td_batch_create(n, arr, ctypes.byref(opt), int(flags), ctypes.byref(b), err, 1024)
+    if st != TD_OK:
+        raise TdError(st, err.value.decode())
+    return b
+
+
+def td_batch_kick(b, e0, directions) -> None:
+    e = _f64(e0).reshape(-1)
+    d = _f64(directions).reshape(-1)
+    if d.size != 3 * e.size:
+        raise ValueError("directions must have shape [n, 3]")
+    _bcheck(b, load().td_batch_kick(b, _ptr(e), _ptr(d)))
+
+
+def td_batch_step(b, n: int, field: Optional[np.ndarray] = None) -> None:
+    f = None if field is None else _f64(field).reshape(-1)
+    if f is not None and f.size != 3 * n:
+        raise ValueError("field must have shape [n, 3]")
+    _bcheck(b, load().td_batch_step(b, int(n), _ptr(f)))
+
+
+def td_batch_get_dipole_series(b, member: int, cap: int) -> np.ndarray:
+    out = np.empty((max(cap, 1), 3))
+    n = ctypes.c_int32()
+    _bcheck(b, load().td_batch_get_dipole_series(b, int(member), _ptr(out), int(cap),
+                                                 ctypes.byref(n)))
+    return out[:min(cap, n.value)]
+
+
+def td_batch_get_charges(b, member: int, n_atoms: int) -> np.ndarray:
+    out = np.empty(n_atoms)
+    _bcheck(b, load().td_batch_get_charges(b, int(member), _ptr(out)))
+    return out
+
+
+def td_batch_get_rho(b, member: int, n_orb: int, with_prev: bool = False):
+    rho = np.empty((n_orb, n_orb), dtype=np.complex128)
+    prev = np.empty((n_orb, n_orb), dtype=np.complex128) if with_prev else None
+    step = ctypes.c_int64()
+    has_prev = ctypes.c_int32()
+    _bcheck(b, load().td_batch_get_rho(b, int(member), rho.ctypes.data_as(_dp),
+                                       None if prev is None else prev.ctypes.data_as(_dp),
+                                       ctypes.byref(step), ctypes.byref(has_prev)))
+    return rho, prev, step.value, bool(has_prev.value)
+
+
+def td_batch_get_info(b) -> dict:
+    info = TdBatchInfo()
+    _bcheck(b, load().td_batch_get_info(b, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def td_batch_destroy(b) -> None:
+    if b:
+        load().td_batch_destroy(b)
 
 
 def _check(ctx, st):
@@ -356,6 +466,48 @@ class Propagator:
         if self.ctx:
             td_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Convenience wrapper owning one batch of trajectories."""
+
+    def __init__(self, systems, dt=0.2, rho0s=None, flags=0, scc_tol=1e-12, scc_maxiter=300):
+        opt = td_default_options()
+        opt.dt = dt
+        opt.scc_tol = scc_tol
+        opt.scc_maxiter = scc_maxiter
+        self.n_atoms = [len(s.q0) for s in systems]
+        self.n_orb = [int(s.orb_offset[-1]) for s in systems]
+        self.b = td_batch_create(systems, opt, rho0s, flags)
+
+    def kick(self, e0, directions):
+        td_batch_kick(self.b, e0, directions)
+
+    def step(self, n, field=None):
+        td_batch_step(self.b, n, field)
+
+    def dipoles(self, member, n):
+        return td_batch_get_dipole_series(self.b, member, n)
+
+    def charges(self, member):
+        return td_batch_get_charges(self.b, member, self.n_atoms[member])
+
+    def rho(self, member, with_prev=False):
+        return td_batch_get_rho(self.b, member, self.n_orb[member], with_prev)
+
+    def info(self):
+        return td_batch_get_info(self.b)
+
+    def close(self):
+        if self.b:
+            td_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

@@ -107,3 +107,22 @@ def test_no_device_is_an_error_not_a_fallback(T):
     with pytest.raises(T.TdError) as e:
         T.td_util_gemm(np.eye(4), np.eye(4))
     assert e.value.status == T.TD_EHIP
+
+
+def test_batch_arguments_rejected_before_device(T):
+    s = W.flake_c24h16()
+    o = T.td_default_options()
+    o.precision = T.TD_SPLIT_BF16
+    with pytest.raises(T.TdError) as e:
+        T.td_batch_create([s, s], o)
+    assert e.value.status == T.TD_ENOTSUP
+    with pytest.raises(T.TdError) as e:
+        T.td_batch_create([s], flags=T.TD_BATCH_TILE_64 | T.TD_BATCH_TILE_128)
+    assert e.value.status == T.TD_EINVAL
+    with pytest.raises(T.TdError) as e:
+        T.td_batch_create([s], flags=64)
+    assert e.value.status == T.TD_EINVAL
+    lib = T.load()
+    assert lib.td_batch_step(None, 1, None) == T.TD_EINVAL
+    assert lib.td_batch_kick(None, None, None) == T.TD_EINVAL
+    assert T.load().td_batch_last_error(None) == b"null batch"

@@ -333,6 +333,32 @@ def small_strip(columns, n_pairs, seed, width=3) -> System:
     raise ValueError("no closed-shell strip of this length")
 
 
+def probe_molecule(target_n, seed) -> System:
+    """C/H strip with close to ``target_n`` orbitals (one member of a probe batch).
+
+    Armchair strips one and three hexagons wide (two-wide strips of these
+    lengths have near-degenerate frontier levels); the width whose length
+    step lands closest to the target is taken. ``seed`` jitters the geometry
+    and the two-centre parameters.
+    """
+    best = None
+    for width, base, per in ((1, 30, 14), (3, 88, 30)):
+        cols = max(2, int(round((target_n - base) / per)) + 2)
+        s = small_strip(cols, 0, seed=seed, width=width)
+        if best is None or abs(s.n_orb - target_n) < abs(best.n_orb - target_n):
+            best = s
+    return best
+
+
+def probe_batch(count, seed=4000, n_lo=60, n_hi=800):
+    """``count`` probe molecules with N_orb ~ uniform in [n_lo, n_hi] and a kick
+    axis drawn from {x, y, z} for each: returns (systems, axes [count, 3])."""
+    rng = np.random.default_rng(seed)
+    targets = rng.integers(n_lo, n_hi + 1, size=count)
+    axes = np.eye(3)[rng.integers(0, 3, size=count)]
+    return [probe_molecule(int(t), seed + 1 + j) for j, t in enumerate(targets)], axes
+
+
 # ----------------------------------------------------------------------------
 # fields and workloads
 # ----------------------------------------------------------------------------
