@@ -61,6 +61,11 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device once (a plain copy kernel of "
                          "known size, to calibrate HBM byte counters)")
+    ap.add_argument("--batched", type=int, default=0,
+                    help="instead of the N_orb=4096 step: time a batch of this many probe "
+                         "trajectories (N_orb ~ U[60, 800]) against solo runs of a sample")
+    ap.add_argument("--batch-flags", type=int, default=0,
+                    help="td_batch_create flags for --batched (1 no graph, 2 / 4 force tiles)")
     ap.add_argument("--validate", type=int, default=0,
                     help="instead of timing: propagate this many steps in FP64 and in "
                          "split-bf16 (--slices) from the same ground state and print the "
@@ -251,6 +256,65 @@ def run(T, w, precision, slices, warmup, steps, field):
     }
 
 
+def batched(args):
+    """Probe batch: member-steps/s of one batch against solo contexts.
+
+    The batch steps all members together (grouped launches, graph replay);
+    the solo figure is the same number of steps of a sample of the members,
+    each in its own context, one after the other, scaled to the whole batch.
+    """
+    import workloads as W
+    from paper_1912_03174_amd import tddftb as T
+
+    count = args.batched
+    log(f"generating {count} probe molecules")
+    systems, axes = W.probe_batch(count)
+    ns = np.array([s.n_orb for s in systems], dtype=np.float64)
+    flop_step = float(np.sum(6.0 * ns ** 3))
+    t0 = time.perf_counter()
+    b = T.Batch(systems, flags=args.batch_flags)
+    init_s = time.perf_counter() - t0
+    log(f"batch created in {init_s:.1f} s")
+    b.kick(np.full(count, 1e-3), axes)
+    if args.warmup:
+        b.step(args.warmup)
+    t0 = time.perf_counter()
+    b.step(args.steps)
+    el = time.perf_counter() - t0
+    info = b.info()
+    b.close()
+    rate = count * args.steps / el
+    # solo contexts on an evenly spaced sample, same steps
+    sample = list(range(0, count, max(1, count // 32)))
+    solo_s = 0.0
+    for m in sample:
+        p = T.Propagator(systems[m])
+        p.kick(1e-3, axes[m])
+        if args.warmup:
+            p.step(args.warmup)
+        t0 = time.perf_counter()
+        p.step(args.steps)
+        solo_s += time.perf_counter() - t0
+        p.close()
+    solo_rate = len(sample) * args.steps / solo_s
+    out = {
+        "metric": "probe-trajectory steps/s, batch of N_orb ~ U[60, 800] (FP64)",
+        "value": rate, "unit": "member-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"probe batch x{count}", "members": count,
+                   "n_orb_min": int(ns.min()), "n_orb_max": int(ns.max()),
+                   "n_orb_mean": float(ns.mean()), "flags": args.batch_flags},
+        "algorithmic_tflops": flop_step * args.steps / el / 1e12,
+        "fp64_peak_frac": flop_step * args.steps / el / 1e12 / FP64_PEAK_TFLOPS,
+        "solo_sample": {"members": len(sample), "member_steps_per_s": solo_rate},
+        "speedup_vs_solo": rate / solo_rate,
+        "init_s": init_s, "tiles": info["bucket_tile"], "bucket_members": info["bucket_members"],
+        "tuning_ms": info["bucket_ms"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -267,6 +331,9 @@ def main():
         return
     if args.validate:
         validate(args)
+        return
+    if args.batched:
+        batched(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
