@@ -92,7 +92,12 @@ __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
   const int gsz = (p.tiles_m - first_m) < GROUP_M ? (p.tiles_m - first_m) : GROUP_M;
   const int in_g = lin - g * group;
   const int m0 = (first_m + in_g % gsz) * BM;
-  const int n0 = (in_g / gsz) * BN;
+  // When the columns below n_split (K = k_hi) and above it (K = k_lo) are
+  // two equal halves, column tiles alternate between the halves, so every
+  // XCD's contiguous range of tiles holds as much long-K as short-K work.
+  const int ci = in_g / gsz;
+  const bool alternate = p.k_lo != p.k_hi && 2 * p.n_split == p.tiles_n * BN;
+  const int n0 = (alternate ? ((ci & 1) ? p.tiles_n / 2 + (ci >> 1) : (ci >> 1)) : ci) * BN;
   const int K = (n0 < p.n_split) ? p.k_hi : p.k_lo;
   const int nk = K / BK;
 
@@ -331,9 +336,89 @@ hipError_t launch_split(hipStream_t st, const SplitGemm& g) {
   return hipGetLastError();
 }
 
+// Same slicing for rows of at most 128 CPL values, two waves per row: each
+// lane keeps its CPL values in registers between the row maximum and the
+// slicing, so the source is read from memory once instead of twice.
+template <int S, int MODE, int CPL>
+__global__ __launch_bounds__(256) void k_slice_rows_cached(SliceSrc src, int rows, int cols,
+                                                           __bf16* out, int ldo, int* exps) {
+  __shared__ double wmax[4];
+  const int row = blockIdx.x * 2 + (threadIdx.x >> 7);
+  const int l = threadIdx.x & 127;
+  const bool live = row < rows;
+  double x[CPL];
+  double m = 0.0;
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    const int c = l + 128 * j;
+    double val = 0.0;
+    if (live && c < cols) {
+      if (MODE == SLICE_PLAIN) {
+        val = src.sign * src.M0[(size_t)row * src.ld0 + c];
+      } else if (MODE == SLICE_SUM) {
+        val = src.M0[(size_t)row * src.ld0 + c] + src.M1[(size_t)row * src.ld1 + c];
+      } else if (MODE == SLICE_RENORM) {
+        val = src.M0[(size_t)row * src.ld0 + c] - src.cs[0] * src.M1[(size_t)row * src.ld1 + c];
+      } else {
+        val = 0.5 * src.M0[(size_t)row * src.ld0 + c] * (src.v[row] + src.v[c]);
+      }
+    }
+    x[j] = val;
+    m = fmax(m, fabs(val));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  m = fmax(wmax[(threadIdx.x >> 7) * 2], wmax[(threadIdx.x >> 7) * 2 + 1]);
+  if (!live) return;
+  int e = 0;
+  if (m > 0.0) frexp(m, &e);
+  if (l == 0) exps[row] = e;
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    const int c = l + 128 * j;
+    if (c < cols) {
+      if (MODE == SLICE_RENORM) src.M0w[(size_t)row * src.ld0 + c] = x[j];
+      double rr = ldexp(x[j], 8 - e);
+      __bf16* o = out + (size_t)row * ldo + (size_t)(c >> 4) * (16 * S) + (c & 15);
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const double sig = rint(rr);
+        o[s * 16] = (__bf16)(float)ldexp(sig, -8 * s);
+        rr = (rr - sig) * 256.0;
+      }
+    }
+  }
+}
+
 template <int S>
 hipError_t launch_slice(hipStream_t st, int mode, const SliceSrc& src, int rows, int cols,
                         __bf16* out, int ldo, int* exps) {
+  if (cols <= 128 * 32) {
+    const dim3 grid((rows + 1) / 2), block(256);
+    switch (mode) {
+      case SLICE_PLAIN:
+        hipLaunchKernelGGL((k_slice_rows_cached<S, SLICE_PLAIN, 32>), grid, block, 0, st, src,
+                           rows, cols, out, ldo, exps);
+        break;
+      case SLICE_SUM:
+        hipLaunchKernelGGL((k_slice_rows_cached<S, SLICE_SUM, 32>), grid, block, 0, st, src, rows,
+                           cols, out, ldo, exps);
+        break;
+      case SLICE_DH:
+        hipLaunchKernelGGL((k_slice_rows_cached<S, SLICE_DH, 32>), grid, block, 0, st, src, rows,
+                           cols, out, ldo, exps);
+        break;
+      case SLICE_RENORM:
+        hipLaunchKernelGGL((k_slice_rows_cached<S, SLICE_RENORM, 32>), grid, block, 0, st, src,
+                           rows, cols, out, ldo, exps);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   const dim3 grid((rows + 3) / 4), block(256);
   switch (mode) {
     case SLICE_PLAIN:
