@@ -66,6 +66,81 @@ typedef __attribute__((address_space(3))) void lds_void;
 // f(r) = r + r/8 to spread the b128 fragment reads over the banks.
 __device__ __forceinline__ int rot(int row) { return row + (row >> 3); }
 
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t lds_u32(const __bf16* p) {
+  return (uint32_t)(uintptr_t)(lds_void*)p;
+}
+
+// All 3 S operand fragments of one K step from LDS in one block that also
+// waits for them (lgkmcnt(0) inside the block, so no read is in flight when
+// the compiler takes the registers). Reading LDS through the compiler
+// would make it wait for every direct-to-LDS load in flight (vmcnt(0)) at
+// the top of the unrolled K loop, where it cannot tell the stages apart;
+// the stage being read is guarded by the explicit waits and the barrier.
+template <int S>
+struct Frags {
+  i32x4 a[S], b0[S], b1[S];
+};
+
+template <int S>
+__device__ __forceinline__ void read_frags(Frags<S>& f, uint32_t base, const uint32_t* ao,
+                                           const uint32_t* bo0, const uint32_t* bo1) {
+  if constexpr (S == 3) {
+    asm volatile("ds_read_b128 %0, %9\n"
+                 "ds_read_b128 %1, %10\n"
+                 "ds_read_b128 %2, %11\n"
+                 "ds_read_b128 %3, %12\n"
+                 "ds_read_b128 %4, %13\n"
+                 "ds_read_b128 %5, %14\n"
+                 "ds_read_b128 %6, %15\n"
+                 "ds_read_b128 %7, %16\n"
+                 "ds_read_b128 %8, %17\n"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(f.a[0]), "=&v"(f.a[1]), "=&v"(f.a[2]), "=&v"(f.b0[0]), "=&v"(f.b0[1]), "=&v"(f.b0[2]), "=&v"(f.b1[0]), "=&v"(f.b1[1]), "=&v"(f.b1[2])
+                 : "v"(base + ao[0]), "v"(base + ao[1]), "v"(base + ao[2]), "v"(base + bo0[0]), "v"(base + bo0[1]), "v"(base + bo0[2]), "v"(base + bo1[0]), "v"(base + bo1[1]), "v"(base + bo1[2])
+                 : "memory");
+  } else if constexpr (S == 4) {
+    asm volatile("ds_read_b128 %0, %12\n"
+                 "ds_read_b128 %1, %13\n"
+                 "ds_read_b128 %2, %14\n"
+                 "ds_read_b128 %3, %15\n"
+                 "ds_read_b128 %4, %16\n"
+                 "ds_read_b128 %5, %17\n"
+                 "ds_read_b128 %6, %18\n"
+                 "ds_read_b128 %7, %19\n"
+                 "ds_read_b128 %8, %20\n"
+                 "ds_read_b128 %9, %21\n"
+                 "ds_read_b128 %10, %22\n"
+                 "ds_read_b128 %11, %23\n"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(f.a[0]), "=&v"(f.a[1]), "=&v"(f.a[2]), "=&v"(f.a[3]), "=&v"(f.b0[0]), "=&v"(f.b0[1]), "=&v"(f.b0[2]), "=&v"(f.b0[3]), "=&v"(f.b1[0]), "=&v"(f.b1[1]), "=&v"(f.b1[2]), "=&v"(f.b1[3])
+                 : "v"(base + ao[0]), "v"(base + ao[1]), "v"(base + ao[2]), "v"(base + ao[3]), "v"(base + bo0[0]), "v"(base + bo0[1]), "v"(base + bo0[2]), "v"(base + bo0[3]), "v"(base + bo1[0]), "v"(base + bo1[1]), "v"(base + bo1[2]), "v"(base + bo1[3])
+                 : "memory");
+  } else {
+    static_assert(S == 5, "3, 4 or 5 slices");
+    asm volatile("ds_read_b128 %0, %15\n"
+                 "ds_read_b128 %1, %16\n"
+                 "ds_read_b128 %2, %17\n"
+                 "ds_read_b128 %3, %18\n"
+                 "ds_read_b128 %4, %19\n"
+                 "ds_read_b128 %5, %20\n"
+                 "ds_read_b128 %6, %21\n"
+                 "ds_read_b128 %7, %22\n"
+                 "ds_read_b128 %8, %23\n"
+                 "ds_read_b128 %9, %24\n"
+                 "ds_read_b128 %10, %25\n"
+                 "ds_read_b128 %11, %26\n"
+                 "ds_read_b128 %12, %27\n"
+                 "ds_read_b128 %13, %28\n"
+                 "ds_read_b128 %14, %29\n"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(f.a[0]), "=&v"(f.a[1]), "=&v"(f.a[2]), "=&v"(f.a[3]), "=&v"(f.a[4]), "=&v"(f.b0[0]), "=&v"(f.b0[1]), "=&v"(f.b0[2]), "=&v"(f.b0[3]), "=&v"(f.b0[4]), "=&v"(f.b1[0]), "=&v"(f.b1[1]), "=&v"(f.b1[2]), "=&v"(f.b1[3]), "=&v"(f.b1[4])
+                 : "v"(base + ao[0]), "v"(base + ao[1]), "v"(base + ao[2]), "v"(base + ao[3]), "v"(base + ao[4]), "v"(base + bo0[0]), "v"(base + bo0[1]), "v"(base + bo0[2]), "v"(base + bo0[3]), "v"(base + bo0[4]), "v"(base + bo1[0]), "v"(base + bo1[1]), "v"(base + bo1[2]), "v"(base + bo1[3]), "v"(base + bo1[4])
+                 : "memory");
+  }
+}
+
 template <int S>
 __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
   // LDS ring of STAGES separate arrays (so the compiler can see that the
@@ -182,6 +257,7 @@ __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
 
   // fragment offsets (elements) inside a stage: logical slot 2 s + lh of a row
   int a_off[S], b_off[2][S];
+  uint32_t ao[S], bo0[S], bo1[S];   // the same offsets in bytes
   {
     const int arow = wm * 32 + l32;
 #pragma unroll
@@ -198,6 +274,12 @@ __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
         b_off[j][sl] = MAT_ELEMS + brow * SLOTS * 8 + ph * 8;
       }
     }
+  }
+#pragma unroll
+  for (int sl = 0; sl < S; ++sl) {
+    ao[sl] = 2u * a_off[sl];
+    bo0[sl] = 2u * b_off[0][sl];
+    bo1[sl] = 2u * b_off[1][sl];
   }
   // One K step on stage RD: wait for this wave's loads of it, barrier (all
   // waves' loads landed and all waves are past the previous step), refill
@@ -216,11 +298,13 @@ __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
     }                                                                                      \
     __builtin_amdgcn_s_barrier();                                                          \
     if ((kt) + STAGES - 1 < nk) TD_ISSUE_STAGE(WR, (kt) + STAGES - 1);                     \
+    Frags<S> fr;                                                                           \
+    read_frags<S>(fr, lds_u32(RD), ao, bo0, bo1);                                          \
     bf16x8 a[S], b[2][S];                                                                  \
     _Pragma("unroll") for (int sl = 0; sl < S; ++sl) {                                     \
-      a[sl] = *reinterpret_cast<const bf16x8*>((RD) + a_off[sl]);                          \
-      _Pragma("unroll") for (int j = 0; j < 2; ++j)                                        \
-        b[j][sl] = *reinterpret_cast<const bf16x8*>((RD) + b_off[j][sl]);                  \
+      a[sl] = __builtin_bit_cast(bf16x8, fr.a[sl]);                                        \
+      b[0][sl] = __builtin_bit_cast(bf16x8, fr.b0[sl]);                                    \
+      b[1][sl] = __builtin_bit_cast(bf16x8, fr.b1[sl]);                                    \
     }                                                                                      \
     _Pragma("unroll") for (int j = 0; j < 2; ++j)                                          \
       acc2[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[j][0], acc2[j], 0, 0, 0);  \
