@@ -63,8 +63,11 @@ typedef __attribute__((address_space(3))) void lds_void;
 // LDS stage layout: [mat][row][2S slots of 8 bf16] -- one K step of the
 // k-blocked global layout, so each direct-to-LDS instruction moves whole
 // 128-byte lines (S = 4) -- with the slots of row r rotated by
-// f(r) = r + r/8 to spread the b128 fragment reads over the banks.
-__device__ __forceinline__ int rot(int row) { return row + (row >> 3); }
+// f(r) = 2 r + r/4. A 128-bit fragment read is served for lanes i..i+3
+// together with lanes 32+i..32+i+3 (rows r..r+3, both k halves): with this
+// rotation those eight 16-byte reads hit eight different bank groups, as
+// do eight or sixteen consecutive lanes.
+__device__ __forceinline__ int rot(int row) { return 2 * row + (row >> 2); }
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
