@@ -270,6 +270,41 @@ TD_API td_status td_batch_get_info(td_batch *b, td_batch_info *info);
 TD_API const char *td_batch_last_error(const td_batch *b);
 TD_API void td_batch_destroy(td_batch *b);
 
+/* ---------------------------------------------------------------- spectra
+ * Spectra from recorded dipole series, computed on the GPU (host pointers
+ * in and out; err receives a message on failure). */
+
+/* Polarizability of kicked runs (Sec. 2.2, Eqs. 17-18), one per series j:
+ *   alpha[j, w] = dt / e0[j] sum_{n < n_t} (mu[j, n] - r[j, n])
+ *                 exp(i omega[w] t_n) exp(-t_n / tau),   t_n = n dt,
+ * with r = ref (a reference run over the same times, e.g. the pump-only
+ * dipole of Sec. 5.1) or, when ref is NULL, r[j, n] = mu[j, 0] (the static
+ * dipole). tau <= 0: no damping. mu, ref: [n_series * n_t], the dipole
+ * component along the kick of each series; e0 [n_series] non-zero; omega
+ * [n_omega]. Outputs [n_series * n_omega]: alpha_re, alpha_im, and
+ * sigma = 4 pi omega / c Im alpha (the series' share of the cross-section;
+ * the isotropic cross-section is the mean over three kick directions). */
+TD_API td_status td_spectrum(int32_t n_series, int32_t n_t, const double *mu, const double *ref,
+                             const double *e0, double dt, double tau, int32_t n_omega,
+                             const double *omega, double *alpha_re, double *alpha_im,
+                             double *sigma, char *err, int32_t errlen);
+
+/* Transient absorption from pump-probe runs (Sec. 5.1): series
+ * j = d * n_avg + a are the probes of delay d (a runs over kick directions
+ * and pump phases), ref[j] the pump-only dipole over the same times (both
+ * along the probe's kick). out[d, w] = 4 pi omega_w / c Im(mean_a
+ * alpha[j, w]) with alpha as in td_spectrum; then, if filter_width > 0, a
+ * Gaussian low-pass along the delays exp(-nu^2 / (2 filter_width^2)) (nu in
+ * cycles per unit time, periodic discrete transform over the n_delay delays
+ * spaced delay_step); then, if ref_delay >= 0, the change against that
+ * delay's spectrum, the end of the pump (Sec. 5.2). out [n_delay * n_omega]. */
+TD_API td_status td_transient_absorption(int32_t n_delay, int32_t n_avg, int32_t n_t,
+                                         const double *mu, const double *ref, const double *e0,
+                                         double dt, double tau, int32_t n_omega,
+                                         const double *omega, int32_t ref_delay,
+                                         double delay_step, double filter_width, double *out,
+                                         char *err, int32_t errlen);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,7 @@ EXPORTED = [
     "td_last_error", "td_status_string", "td_destroy", "td_util_gemm",
     "td_batch_create", "td_batch_kick", "td_batch_step", "td_batch_get_dipole_series",
     "td_batch_get_charges", "td_batch_get_rho", "td_batch_get_info", "td_batch_last_error",
-    "td_batch_destroy",
+    "td_batch_destroy", "td_spectrum", "td_transient_absorption",
 ]
 TD_BATCH_NO_GRAPH, TD_BATCH_TILE_128, TD_BATCH_TILE_64 = 1, 2, 4
 TD_BATCH_BUCKETS = 8
@@ -122,6 +122,15 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "td_batch_get_info": (ctypes.c_int32, [vp, ctypes.POINTER(TdBatchInfo)]),
         "td_batch_last_error": (ctypes.c_char_p, [vp]),
         "td_batch_destroy": (None, [vp]),
+        "td_spectrum": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_int32, _dp,
+                                         _dp, _dp, _dp, ctypes.c_char_p, ctypes.c_int32]),
+        "td_transient_absorption": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32,
+                                                     ctypes.c_int32, _dp, _dp, _dp,
+                                                     ctypes.c_double, ctypes.c_double,
+                                                     ctypes.c_int32, _dp, ctypes.c_int32,
+                                                     ctypes.c_double, ctypes.c_double, _dp,
+                                                     ctypes.c_char_p, ctypes.c_int32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -472,6 +481,47 @@ class Propagator:
             self.close()
         except Exception:
             pass
+
+
+def td_spectrum(mu, e0, dt, omega, ref=None, tau=0.0):
+    """td_spectrum: mu [n_series, n_t] (or [n_t]), e0 scalar or [n_series];
+    returns (alpha [n_series, n_omega] complex, sigma [n_series, n_omega])."""
+    m = np.atleast_2d(_f64(mu))
+    r = None if ref is None else np.atleast_2d(_f64(ref))
+    if r is not None and r.shape != m.shape:
+        raise ValueError("ref must have the shape of mu")
+    J, T = m.shape
+    e = _f64(np.broadcast_to(np.asarray(e0, dtype=np.float64), (J,)))
+    w = _f64(omega).reshape(-1)
+    are, aim, sig = (np.empty((J, w.size)) for _ in range(3))
+    err = ctypes.create_string_buffer(1024)
+    st = load().td_spectrum(J, T, _ptr(m), _ptr(r), _ptr(e), float(dt), float(tau), w.size,
+                            _ptr(w), _ptr(are), _ptr(aim), _ptr(sig), err, 1024)
+    if st != TD_OK:
+        raise TdError(st, err.value.decode())
+    return are + 1j * aim, sig
+
+
+def td_transient_absorption(mu, ref, e0, dt, omega, tau=0.0, ref_delay=-1, delay_step=0.0,
+                            filter_width=0.0):
+    """td_transient_absorption: mu, ref [n_delay, n_avg, n_t]; e0 scalar or
+    [n_delay, n_avg]; returns [n_delay, n_omega]."""
+    m = _f64(mu)
+    r = _f64(ref)
+    if m.ndim != 3 or r.shape != m.shape:
+        raise ValueError("mu and ref must be [n_delay, n_avg, n_t]")
+    D, A, T = m.shape
+    e = _f64(np.broadcast_to(np.asarray(e0, dtype=np.float64), (D, A)))
+    w = _f64(omega).reshape(-1)
+    out = np.empty((D, w.size))
+    err = ctypes.create_string_buffer(1024)
+    st = load().td_transient_absorption(D, A, T, _ptr(m), _ptr(r), _ptr(e), float(dt),
+                                        float(tau), w.size, _ptr(w), int(ref_delay),
+                                        float(delay_step), float(filter_width), _ptr(out), err,
+                                        1024)
+    if st != TD_OK:
+        raise TdError(st, err.value.decode())
+    return out
 
 
 class Batch:

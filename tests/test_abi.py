@@ -126,3 +126,17 @@ def test_batch_arguments_rejected_before_device(T):
     assert lib.td_batch_step(None, 1, None) == T.TD_EINVAL
     assert lib.td_batch_kick(None, None, None) == T.TD_EINVAL
     assert T.load().td_batch_last_error(None) == b"null batch"
+
+
+def test_spectrum_arguments_rejected_before_device(T):
+    mu = np.zeros((2, 10))
+    with pytest.raises(T.TdError) as e:
+        T.td_spectrum(mu, [1e-3, 0.0], 0.2, [0.1, 0.2])
+    assert e.value.status == T.TD_EINVAL
+    with pytest.raises(T.TdError) as e:
+        T.td_spectrum(np.zeros((2, 1)), 1e-3, 0.2, [0.1])
+    assert e.value.status == T.TD_EINVAL
+    with pytest.raises(T.TdError) as e:
+        T.td_transient_absorption(np.zeros((3, 2, 10)), np.zeros((3, 2, 10)), 1e-3, 0.2, [0.1],
+                                  ref_delay=5)
+    assert e.value.status == T.TD_EINVAL

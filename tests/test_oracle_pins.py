@@ -416,3 +416,61 @@ def test_trace_renormalisation(flake, flake_gs):
     fixed = O.renormalise_delta(off, rho_ref, s.S, s.n_elec)
     assert abs(O.electron_count(rho_ref + fixed, s.S) - s.n_elec) < 1e-12
     assert np.abs(fixed - delta).max() < 1e-14
+
+
+# ---------------------------------------------------------------- transient absorption
+
+def test_effective_polarizability_closed_form():
+    """A damped probe-minus-pump signal A sin(w0 t) transforms to a sum of two
+    geometric series: sum_n z^n = (1 - z^N) / (1 - z), z = exp((i w +- i w0 - 1/tau) dt)."""
+    dt, n, w0, amp, tau, e0 = 0.2, 3000, 0.37, 2e-4, 150.0, 1e-3
+    t = np.arange(n) * dt
+    pump = 0.05 * np.cos(0.11 * t) + 0.3             # pump-only signal, cancelled exactly
+    probe = pump + amp * np.sin(w0 * t)
+    omega = np.linspace(0.05, 1.0, 97)
+    alpha = O.effective_polarizability(t, probe, pump, e0, omega, tau=tau)
+
+    def geo(z):
+        return (1.0 - z ** n) / (1.0 - z)
+
+    zp = np.exp((1j * (omega + w0) - 1.0 / tau) * dt)
+    zm = np.exp((1j * (omega - w0) - 1.0 / tau) * dt)
+    exact = amp * (geo(zp) - geo(zm)) / (2j) * dt / e0
+    assert np.abs(alpha - exact).max() < 1e-10 * np.abs(exact).max()
+    # absorption peak at w0 with Im alpha > 0
+    k = int(np.argmax(np.imag(alpha)))
+    assert abs(omega[k] - w0) < 0.02 and np.imag(alpha[k]) > 0
+
+
+def test_phase_average_cancels_pump_probe_beat():
+    """Averaging over four pump phases 0, pi/2, pi, 3 pi/2 removes a response
+    term that carries the pump phase (Sec. 5.1), keeping the phase-free part."""
+    dt, n, e0 = 0.2, 2000, 1e-3
+    t = np.arange(n) * dt
+    omega = np.linspace(0.1, 0.8, 40)
+    zero = np.zeros(n)
+    base = 1e-4 * np.sin(0.4 * t)
+    alphas = []
+    for phi in (0.0, 0.5 * np.pi, np.pi, 1.5 * np.pi):
+        beat = 3e-5 * np.sin(0.25 * t + phi)
+        alphas.append(O.effective_polarizability(t, base + beat, zero, e0, omega))
+    avg = O.transient_cross_section(omega, np.array(alphas)[None, :, :])[0]
+    clean = O.transient_cross_section(
+        omega, O.effective_polarizability(t, base, zero, e0, omega)[None, None, :])[0]
+    assert np.abs(avg - clean).max() < 1e-12 * np.abs(clean).max()
+    single = O.transient_cross_section(omega, np.array(alphas[:1])[None, :, :])[0]
+    assert np.abs(single - clean).max() > 1e-3 * np.abs(clean).max()
+
+
+def test_gaussian_delay_filter_and_delta_absorbance():
+    n, step, width = 64, 5.0, 0.01
+    const = np.full((n, 3), 2.5)
+    assert np.abs(O.gaussian_filter_delay(const, step, width) - 2.5).max() < 1e-13
+    k = 5                                             # a discrete-transform bin
+    nu = k / (n * step)
+    wave = np.cos(2 * np.pi * k * np.arange(n) / n)[:, None] * np.ones((1, 2))
+    out = O.gaussian_filter_delay(wave, step, width)
+    assert np.abs(out - np.exp(-nu ** 2 / (2 * width ** 2)) * wave).max() < 1e-13
+    sig = np.random.default_rng(1).standard_normal((7, 4))
+    d = O.delta_absorbance(sig, 2)
+    assert np.all(d[2] == 0.0) and np.allclose(d[5], sig[5] - sig[2])
