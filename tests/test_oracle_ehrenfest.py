@@ -1,0 +1,139 @@
+"""Pins of the Ehrenfest oracle (moving nuclei) against closed forms,
+numerical derivatives and conservation laws."""
+import dataclasses
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle as O
+import oracle.ehrenfest as OE
+import workloads as W
+
+
+@pytest.fixture(scope="module")
+def benzene():
+    s = W.benzene()
+    return s, W.two_centre_model(s)
+
+
+def test_model_rebuilds_the_input_matrices(benzene):
+    """The oracle's two-centre evaluation reproduces S, H0 and gamma of the input."""
+    for s in (benzene[0], W.flake_c24h16()):
+        m = W.two_centre_model(s)
+        S, H0 = OE.model_matrices(m, s.positions)
+        assert np.abs(S - s.S).max() < 1e-14 and np.abs(H0 - s.H0).max() < 1e-14
+        assert np.abs(OE.gamma_matrix(s.positions, m["hubbard_u"]) - s.gamma).max() < 1e-14
+
+
+def test_fd_gradient_matches_analytic_two_centre_derivatives(benzene):
+    """Central differences (Eq. 20) against the analytic derivative of the
+    s-s integral c f exp(-r/L) (-l / L) and of the s-p integral
+    c f exp(-r/L) [(delta_kj - l_k l_j) / r - l_k l_j / L]."""
+    s, m = benzene
+    GS, GH = OE.fd_gradients(m, s.positions)
+    off = OE.orbital_offsets(m)
+    L = m["decay"]
+    worst = 0.0
+    for a, b in [(0, 1), (0, 3), (1, 7), (6, 2)]:          # C-C, C-C, C-H, H-C pairs
+        d = s.positions[b] - s.positions[a]
+        r = np.linalg.norm(d)
+        l = d / r
+        sa, sb = m["species"][a], m["species"][b]
+        f = m["scale_s"][a, b] * np.exp(-r / L)
+        c = m["sk_s"][sa, sb, 0]
+        exact_ss = c * f * (-l / L)
+        got = GS[:, off[a], off[b]]
+        worst = max(worst, np.abs(got - exact_ss).max() / np.abs(exact_ss).max())
+        if m["species_norb"][sb] == 4:
+            csp = m["sk_s"][sa, sb, 1]
+            for k in range(3):
+                exact = csp * f * ((np.eye(3)[k] - l[k] * l) / r - l[k] * l / L)
+                got = GS[:, off[a], off[b] + 1 + k]
+                worst = max(worst, np.abs(got - exact).max() / np.abs(csp * f / L))
+    assert worst < 1e-8
+
+
+def _scc_energy(s, m, positions):
+    S, H0 = OE.model_matrices(m, positions)
+    gamma = OE.gamma_matrix(positions, m["hubbard_u"])
+    sys2 = dataclasses.replace(s, positions=positions, S=S, H0=H0, gamma=gamma)
+    gs = O.ground_state(sys2, tol=1e-13)
+    return gs, sys2, O.energy(gs.rho, H0, gamma, gs.dq, positions)
+
+
+def test_ground_state_force_is_minus_energy_gradient(benzene):
+    """At the SCC ground state the force of Eq. 15 (velocity terms aside)
+    equals -dE/dR of the self-consistent energy, by central differences."""
+    s, m = benzene
+    gs, sys0, _ = _scc_energy(s, m, s.positions)
+    S, H0 = sys0.S, sys0.H0
+    Sinv = O.inverse_overlap(S)
+    GS, GH = OE.fd_gradients(m, s.positions)
+    atom_of, _ = OE.orbital_types(m)
+    v_orb = (sys0.gamma @ gs.dq)[atom_of]
+    H = H0 + 0.5 * S * (v_orb[:, None] + v_orb[None, :])
+    F = OE.forces(gs.rho, H, Sinv, GS, GH, v_orb, gs.dq, s.positions, m["hubbard_u"], None, m)
+    h = 1e-3
+    for a, k in [(0, 0), (2, 1), (7, 0), (10, 2)]:
+        p = s.positions.copy()
+        p[a, k] += h
+        ep = _scc_energy(s, m, p)[2]
+        p[a, k] -= 2 * h
+        em = _scc_energy(s, m, p)[2]
+        num = -(ep - em) / (2 * h)
+        assert abs(F[a, k] - num) < 1e-5 * np.abs(F).max() + 1e-9, (a, k, F[a, k], num)
+    assert np.abs(F.sum(axis=0)).max() < 1e-10 * np.abs(F).max()
+
+
+def test_total_energy_conserved(benzene):
+    """Electronic plus nuclear kinetic energy is conserved (no field) to the
+    integrators' second order, while energy flows between them."""
+    s, m = benzene
+    gs = O.ground_state(s, tol=1e-13)
+    Sinv = O.inverse_overlap(s.S)
+    rho = O.kick(gs.rho, s.S, Sinv, s.positions, s.orb_offset, 0.05, (1.0, 0.3, 0.0))
+    vel = W.thermal_velocities(s, 2000.0, seed=5)
+    err = []
+    for dt, n in ((0.2, 200), (0.1, 400)):
+        tr = OE.propagate(s, m, rho, vel, n, dt)
+        etot = tr.e_elec + tr.e_kin
+        swing = np.abs(tr.e_kin - tr.e_kin[0]).max()
+        assert swing > 1e-2                               # real energy exchange
+        err.append(np.abs(etot - etot[0]).max())
+        assert err[-1] < 3e-2 * swing
+        # Tr(rho S) with moving S: kept by the D terms up to the integrator's error
+        err.append(np.abs(tr.electrons - s.n_elec).max())
+        assert err[-1] < 1e-4
+    assert err[0] / err[2] > 3.5 and err[1] / err[3] > 3.5   # second order in dt
+
+
+def test_frozen_nuclei_limit(benzene):
+    """Huge masses and no initial velocity: the trajectory is the clamped one."""
+    s, m = benzene
+    heavy = dict(m, mass=m["mass"] * 1e12)
+    gs = O.ground_state(s, tol=1e-13)
+    Sinv = O.inverse_overlap(s.S)
+    rho = O.kick(gs.rho, s.S, Sinv, s.positions, s.orb_offset, 1e-2, (0.0, 1.0, 0.0))
+    tr = OE.propagate(s, heavy, rho, np.zeros((s.n_atoms, 3)), 200, 0.2)
+    ref = O.propagate(s, rho, 200, 0.2, Sinv=Sinv, record_energy=False)
+    assert np.abs(tr.dipoles - ref.dipoles).max() < 1e-9 * np.abs(ref.dipoles - ref.dipoles[0]).max()
+
+
+def test_nac_sums_to_overlap_derivative(benzene):
+    """D + D^T = dS/dt along any motion (the two atoms of each pair carry
+    the derivative between them), and D is antisymmetric when all atoms move
+    with one velocity (Sec. 2.1, remark b: unitary evolution)."""
+    s, m = benzene
+    GS, _ = OE.fd_gradients(m, s.positions)
+    atom_of, _ = OE.orbital_types(m)
+    vel = np.random.default_rng(7).standard_normal((s.n_atoms, 3)) * 0.01
+    D = OE.nac(GS, vel, atom_of)
+    h = 1e-4
+    Sp, _ = OE.model_matrices(m, s.positions + h * vel)
+    Sm, _ = OE.model_matrices(m, s.positions - h * vel)
+    sdot = (Sp - Sm) / (2 * h)
+    assert np.abs(D + D.T - sdot).max() < 1e-8 * np.abs(sdot).max()
+    assert np.abs(np.diag(D)).max() == 0.0
+    Du = OE.nac(GS, np.tile([0.02, -0.01, 0.005], (s.n_atoms, 1)), atom_of)
+    assert np.abs(Du + Du.T).max() < 1e-9 * np.abs(Du).max()

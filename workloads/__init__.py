@@ -72,6 +72,7 @@ class System:
     q0: np.ndarray           # [n_atoms]
     n_elec: int              # closed shell, even
     name: str = ""
+    seed: int = 0            # seed of the two-centre scale factors (see two_centre_model)
 
     @property
     def n_atoms(self) -> int:
@@ -244,12 +245,7 @@ def _two_centre(species, positions, table, jit):
 
 def build_matrices(species, positions, seed):
     """(orb_offset, S, H0, gamma) for atoms at ``positions`` (bohr)."""
-    rng = np.random.default_rng(seed + 7919)
-    na = len(species)
-    jit_s = np.triu(rng.uniform(0.95, 1.05, size=(na, na)), 1)
-    jit_s = jit_s + jit_s.T
-    jit_h = np.triu(rng.uniform(0.95, 1.05, size=(na, na)), 1)
-    jit_h = jit_h + jit_h.T
+    jit_s, jit_h = pair_scales(len(species), seed)
     off, S = _two_centre(species, positions, S_TABLE, jit_s)
     _, H0 = _two_centre(species, positions, H_TABLE, jit_h)
     n = int(off[-1])
@@ -272,7 +268,64 @@ def make_system(species, positions, seed, name="") -> System:
         raise ValueError("open-shell electron count")
     return System(species=list(species), positions=np.ascontiguousarray(positions),
                   orb_offset=off, S=S, H0=H0, gamma=gamma, q0=q0, n_elec=n_elec,
-                  name=name)
+                  name=name, seed=seed)
+
+
+AMU = 1822.888486209           # electron masses per atomic mass unit
+MASS_AMU = dict(C=12.0, H=1.0)
+
+
+def pair_scales(n_atoms, seed):
+    """The seeded per-atom-pair factors of the overlap and of H0 (symmetric,
+    [0.95, 1.05] off the diagonal, 0 on it), as used by build_matrices."""
+    rng = np.random.default_rng(seed + 7919)
+    jit_s = np.triu(rng.uniform(0.95, 1.05, size=(n_atoms, n_atoms)), 1)
+    jit_s = jit_s + jit_s.T
+    jit_h = np.triu(rng.uniform(0.95, 1.05, size=(n_atoms, n_atoms)), 1)
+    jit_h = jit_h + jit_h.T
+    return jit_s, jit_h
+
+
+def two_centre_model(system: System) -> dict:
+    """The parameters S and H0 of ``system`` are built from, as plain arrays,
+    so S(R) and H0(R) can be rebuilt at other positions (moving nuclei).
+
+    Species index 0 = C (s, px, py, pz), 1 = H (s). ``sk_s`` / ``sk_h``
+    [2, 2, 4]: for the ordered species pair (i, j) the prefactors of
+    (ss sigma, sp sigma with s on i and p on j, pp sigma, pp pi); each
+    integral is prefactor x exp(-r / decay) x the Slater-Koster angular
+    factor (direction cosines from the first atom to the second) x the
+    pair's scale factor. ``onsite`` [2, 2]: H0 on-site s and p energies.
+    ``mass`` in electron masses."""
+    idx = {"C": 0, "H": 1}
+    sk_s = np.zeros((2, 2, 4))
+    sk_h = np.zeros((2, 2, 4))
+    for tab, out in ((S_TABLE, sk_s), (H_TABLE, sk_h)):
+        out[0, 0] = [tab["CC"]["ss"], tab["CC"]["sp"], tab["CC"]["pps"], tab["CC"]["ppp"]]
+        out[0, 1, 0] = out[1, 0, 0] = tab["CH"]["ss"]
+        out[1, 0, 1] = tab["CH"]["sp"]           # s on H, p on C
+        out[1, 1, 0] = tab["HH"]["ss"]
+    jit_s, jit_h = pair_scales(system.n_atoms, system.seed)
+    return dict(
+        species=np.array([idx[x] for x in system.species], dtype=np.int32),
+        species_norb=np.array([4, 1], dtype=np.int32),
+        sk_s=sk_s, sk_h=sk_h, decay=DECAY_A * ANGSTROM,
+        scale_s=jit_s, scale_h=jit_h,
+        onsite=np.array([[ONSITE["s"], ONSITE["p"]], [ONSITE["s"], ONSITE["p"]]]),
+        hubbard_u=HUBBARD_U,
+        mass=np.array([MASS_AMU["C"], MASS_AMU["H"]]) * AMU,
+    )
+
+
+def thermal_velocities(system: System, kelvin, seed):
+    """Seeded Maxwell-Boltzmann velocities (bohr / au time) at ``kelvin``,
+    with the centre-of-mass motion removed."""
+    rng = np.random.default_rng(seed)
+    kb = 3.166811563e-6                      # hartree per kelvin
+    m = np.array([MASS_AMU[x] for x in system.species]) * AMU
+    v = rng.standard_normal((system.n_atoms, 3)) * np.sqrt(kb * kelvin / m)[:, None]
+    v -= (m[:, None] * v).sum(axis=0) / m.sum()
+    return v
 
 
 def flake_c24h16(seed=1001) -> System:
