@@ -197,8 +197,10 @@ TD_API td_status td_get_kernel_time(td_ctx *ctx, int32_t kind, double *total_ms,
                                     int64_t *launches);
 TD_API td_status td_reset_kernel_time(td_ctx *ctx);
 
-/* Ehrenfest forces (Sec. 2.1, Eq. 15): not available with clamped nuclei;
- * returns TD_ENOTSUP. */
+/* Ehrenfest forces (Sec. 2.1, Eq. 15) on the nuclei [n_atoms * 3] for the
+ * current density and positions at zero field (a moving-nuclei context,
+ * see td_create_ehrenfest); TD_ENOTSUP for clamped-nuclei contexts, which
+ * carry no model of S(R) and H0(R). */
 TD_API td_status td_get_forces(td_ctx *ctx, double *forces);
 
 TD_API const char *td_last_error(const td_ctx *ctx);
@@ -212,6 +214,66 @@ TD_API void td_destroy(td_ctx *ctx);
 TD_API td_status td_util_gemm(int32_t precision, int32_t n_slices, int32_t m, int32_t n,
                               int32_t k, const double *A, const double *B, double *C,
                               char *err, int32_t errlen);
+
+/* ---------------------------------------------------------------- moving nuclei
+ * Ehrenfest dynamics (Sec. 2.1, Eqs. 9-15; Sec. 2.3): S, H0 and gamma are
+ * rebuilt every step from a two-centre model at the current positions, the
+ * density follows Eq. 10 with the non-adiabatic coupling
+ * D_uv = v_B . grad_B S_uv (u on A != B, v on B; Eq. 14; gradients by
+ * central differences with step eps^(1/4), Eq. 20), and the nuclei follow
+ * velocity Verlet with the Ehrenfest force of Eq. 15 without its velocity
+ * terms (as the paper's implementation), the overlap terms taken as
+ * +1/2 Re Tr{rho ((grad S) S^-1 H + H S^-1 (grad S))} (the sign that
+ * conserves electronic plus nuclear kinetic energy and reduces to the
+ * ground-state energy gradient), the SCC term with the Hamiltonian's full
+ * atomic potential (gamma dq + R . E). No repulsive energy. */
+
+/* Two-centre model: every off-site integral between orbital i of atom a
+ * and orbital j of atom b at d = R_b - R_a is
+ *   prefactor x exp(-|d| / decay) x Slater-Koster angular factor x scale[a, b]
+ * with the prefactors of the ordered species pair (sa, sb):
+ * (ss sigma, sp sigma for s on a and p on b, pp sigma, pp pi); the p-on-a,
+ * s-on-b element uses the (sb, sa) sp prefactor with d reversed. On-site:
+ * S = 1, H0 = onsite[s][0] (s) or onsite[s][1] (p), no on-site coupling.
+ * gamma_AB = 1 / sqrt(r^2 + hubbard_u^-2). Orbitals per atom: s, or s,
+ * p_x, p_y, p_z, in that order, consistent with td_system.orb_offset. */
+typedef struct {
+  int32_t n_species;
+  const int32_t *species;        /* [n_atoms], values in [0, n_species)              */
+  const int32_t *species_norb;   /* [n_species]: 1 or 4                              */
+  const double *sk_s;            /* [n_species * n_species * 4] overlap prefactors   */
+  const double *sk_h;            /* [n_species * n_species * 4] H0 prefactors        */
+  double decay;                  /* bohr, > 0                                        */
+  const double *scale_s;         /* [n_atoms * n_atoms] symmetric pair factors       */
+  const double *scale_h;         /* [n_atoms * n_atoms]                              */
+  const double *onsite;          /* [n_species * 2] hartree                          */
+  double hubbard_u;              /* hartree, > 0                                     */
+  const double *mass;            /* [n_species] electron masses, > 0                 */
+} td_model;
+
+/* Creates a context with moving nuclei. sys gives positions, orb_offset,
+ * q0, the occupations and optionally rho0 as for td_create; its S, H0 and
+ * gamma are ignored (built from the model, on the GPU). velocities
+ * [n_atoms * 3] bohr per au of time (NULL: at rest). FP64 precision only
+ * (TD_ENOTSUP otherwise). td_step then advances electrons and nuclei with
+ * the same dt; td_kick, td_get_rho / td_set_rho act on the electrons and
+ * keep the nuclei. */
+TD_API td_status td_create_ehrenfest(const td_system *sys, const td_model *model,
+                                     const double *velocities, const td_options *opt,
+                                     td_ctx **out, char *err, int32_t errlen);
+
+/* Nuclear state of a moving-nuclei context: positions [n_atoms * 3] of
+ * the current density; velocities [n_atoms * 3] as velocity Verlet keeps
+ * them: the initial velocities before the first step, afterwards half a
+ * step behind the positions (v_{n-1/2}). Any pointer may be NULL. */
+TD_API td_status td_get_nuclei(td_ctx *ctx, double *positions, double *velocities);
+
+/* Per step of the last td_step on a moving-nuclei context: electronic
+ * energy e_el[k] (as td_get_energy, at the step's field) of the density
+ * entering step k and the nuclear kinetic energy e_kin[k] of the velocities
+ * at that step; k < min(cap, n); *n_out = number recorded. */
+TD_API td_status td_get_energy_series(td_ctx *ctx, double *e_el, double *e_kin, int32_t cap,
+                                      int32_t *n_out);
 
 /* ---------------------------------------------------------------- batches
  * Many independent trajectories of different sizes stepped together, as in

@@ -93,6 +93,45 @@ hipError_t batch_leapfrog(hipStream_t s, const BatchMember* mem, const BatchPair
 // *kstep += 1, or = 0 (plain kernels, so they can be captured in a graph).
 hipError_t batch_tick(hipStream_t s, int* kstep, int reset);
 
+// ---------------------------------------------------------------- moving nuclei
+// Two-centre model on the device (species-indexed tables, see td_model).
+struct ModelArgs {
+  const int* species;      // [na]
+  const int* norb;         // [nsp]: 1 or 4
+  const int* orb_off;      // [na + 1]
+  const double* sk_s;      // [nsp * nsp * 4]
+  const double* sk_h;
+  const double* scale_s;   // [na * na]
+  const double* scale_h;
+  const double* onsite;    // [nsp * 2]
+  int na, nsp;
+  double decay;            // bohr
+  double fd_step;          // central-difference step (bohr)
+};
+// S, H0 (np x np, n x n block written) and their column-atom gradients
+// GS, GH (3 consecutive np x np matrices each) at positions pos [na * 3].
+hipError_t model_build(hipStream_t s, const ModelArgs& m, const double* pos, double* S,
+                       double* H0, double* GS, double* GH, int np);
+// gamma [na x na] and dgamma [na x na x 3] (d gamma_AB / d R_A).
+hipError_t gamma_build(hipStream_t s, const double* pos, int na, double u, double* gamma,
+                       double* dgamma);
+// D = sum_k vel[atom(v)][k] GS[k] on the n x n block of the np x np D.
+hipError_t nac_build(hipStream_t s, const double* GS, const double* vel, const int* atom_of,
+                     int n, int np, double* D);
+// Wide X += -i Z.
+hipError_t add_minus_i(hipStream_t s, double* X, const double* Z, int np);
+// Forces F [na x 3] (Ehrenfest, without velocity terms).
+hipError_t ehrenfest_forces(hipStream_t s, const double* rho, int ldr, const double* W,
+                            const double* GS, const double* GH, const double* vorb,
+                            const int* orb_off, const double* dq, const double* dgamma,
+                            const double* E, int na, int n, int np, double* F);
+// vel += h F / M; pos += dt vel; out[0] = kinetic energy of vel + h F / M.
+hipError_t kick_nuclei(hipStream_t s, double* vel, const double* F, const int* species,
+                       const double* mass, int na, double h);
+hipError_t drift_nuclei(hipStream_t s, double* pos, const double* vel, int na, double dt);
+hipError_t kinetic_energy(hipStream_t s, const double* vel, const double* F, const int* species,
+                          const double* mass, int na, double h, double* out);
+
 // ---------------------------------------------------------------- O(n^2) kernels
 // out[r] = sum_c X[r, c] * Y[r, c] for r < rows (cols multiple of 2).
 hipError_t rowdot(hipStream_t s, const double* X, int ldx, const double* Y, int ldy,

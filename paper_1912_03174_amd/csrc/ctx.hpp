@@ -50,6 +50,20 @@ struct td_ctx {
   double *stage = nullptr;     // np x 2np scratch
   __bf16 *sl_sinv = nullptr, *sl_dh = nullptr, *sl_L2 = nullptr, *sl_R2 = nullptr;
   int *e_sinv = nullptr, *e_dh = nullptr, *e_L2 = nullptr, *e_R2 = nullptr;
+  // moving nuclei (Ehrenfest); positions live in pos (device) and pos_h
+  bool ehr = false;
+  bool vel_half = false;       // vel holds v_{n-1/2} (else v_n, before the first step)
+  int nsp = 0;
+  double decay = 0.0, hub_u = 0.0;
+  int *species = nullptr, *norb = nullptr, *atom_of = nullptr;
+  double *sk_s = nullptr, *sk_h = nullptr, *scale_s = nullptr, *scale_h = nullptr;
+  double *onsite = nullptr, *mass = nullptr;
+  double *GS = nullptr, *GH = nullptr;   // 3 np x np each
+  double *W = nullptr, *Dm = nullptr;    // np x np
+  double *Z = nullptr;                   // np x 2np
+  double *dgamma = nullptr;              // na x na x 3
+  double *vel = nullptr, *F = nullptr;   // na x 3
+  double *e_kin = nullptr, *e_el = nullptr;   // per-step series (dip_cap)
   // profiling
   std::vector<hipEvent_t> ev;
   double kt_ms[TD_KT_COUNT] = {0, 0, 0, 0};

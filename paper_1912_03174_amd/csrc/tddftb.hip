@@ -66,6 +66,18 @@ void free_all(td_ctx* c) {
     if (*b) hipFree(*b);
     *b = nullptr;
   }
+  double** ebufs[] = {&c->sk_s, &c->sk_h, &c->scale_s, &c->scale_h, &c->onsite, &c->mass,
+                      &c->GS, &c->GH, &c->W, &c->Dm, &c->Z, &c->dgamma, &c->vel, &c->F,
+                      &c->e_kin, &c->e_el};
+  for (double** b : ebufs) {
+    if (*b) hipFree(*b);
+    *b = nullptr;
+  }
+  int** eib[] = {&c->species, &c->norb, &c->atom_of};
+  for (int** b : eib) {
+    if (*b) hipFree(*b);
+    *b = nullptr;
+  }
   if (c->orb_off) hipFree(c->orb_off);
   c->orb_off = nullptr;
   for (hipEvent_t e : c->ev) hipEventDestroy(e);
@@ -116,13 +128,18 @@ void refresh(td_ctx* c) {
 
 // S^-1 by the Newton-Schulz iteration X <- X (2 - S X), X_0 = I / g with g
 // a Gershgorin bound of the largest eigenvalue of S.
-void inverse_overlap(td_ctx* c) {
+// With `warm`, the iteration starts from the current S^-1 (the inverse of a
+// nearby S, as after a nuclear step).
+void inverse_overlap(td_ctx* c, bool warm = false) {
   const int n = c->n, np = c->np;
-  HIPCHK(c, td::gershgorin(c->stream, c->S, np, n, c->work1, c->work2, c->scal + SC_BOUNDS));
-  double b[2];
-  read_scal(c, SC_BOUNDS, b, 2);
-  REQUIRE(c, std::isfinite(b[1]) && b[1] > 0, TD_ENOTPOSDEF, "S has no positive spectrum bound");
-  HIPCHK(c, td::scaled_identity(c->stream, c->Sinv, np, n, 1.0 / b[1]));
+  if (!warm) {
+    HIPCHK(c, td::gershgorin(c->stream, c->S, np, n, c->work1, c->work2, c->scal + SC_BOUNDS));
+    double b[2];
+    read_scal(c, SC_BOUNDS, b, 2);
+    REQUIRE(c, std::isfinite(b[1]) && b[1] > 0, TD_ENOTPOSDEF,
+            "S has no positive spectrum bound");
+    HIPCHK(c, td::scaled_identity(c->stream, c->Sinv, np, n, 1.0 / b[1]));
+  }
   double prev = INFINITY, res = INFINITY;
   int it = 0;
   for (it = 1; it <= 200; ++it) {
@@ -579,6 +596,82 @@ void create_impl(td_ctx* c, const td_system* s_in, const td_options* o) {
   refresh(c);
 }
 
+// ---------------------------------------------------------------- moving nuclei
+td::ModelArgs model_args(td_ctx* c) {
+  td::ModelArgs m;
+  m.species = c->species;
+  m.norb = c->norb;
+  m.orb_off = c->orb_off;
+  m.sk_s = c->sk_s;
+  m.sk_h = c->sk_h;
+  m.scale_s = c->scale_s;
+  m.scale_h = c->scale_h;
+  m.onsite = c->onsite;
+  m.na = c->na;
+  m.nsp = c->nsp;
+  m.decay = c->decay;
+  m.fd_step = std::pow(2.220446049250313e-16, 0.25);   // eps^(1/4) (Sec. 2.3, Eq. 20)
+  return m;
+}
+
+// S, H0, their gradients, gamma and S^-1 at the current positions.
+void rebuild_model(td_ctx* c, bool warm) {
+  HIPCHK(c, td::model_build(c->stream, model_args(c), c->pos, c->S, c->H0, c->GS, c->GH, c->np));
+  HIPCHK(c, td::gamma_build(c->stream, c->pos, c->na, c->hub_u, c->gamma, c->dgamma));
+  inverse_overlap(c, warm);
+}
+
+// Charges (dipole -> mu), H with field E, X = (S^-1 H) rho_cur, W = sym Re X and
+// the forces F of the current state (Sec. 2.1, Eq. 15 without velocity terms).
+void ehr_forces(td_ctx* c, const double* E, double* mu, double* energy3) {
+  hipStream_t st = c->stream;
+  const int np = c->np, na = c->na;
+  mulliken(c, mu);
+  if (energy3) {
+    HIPCHK(c, td::potential(st, c->gamma, c->dq, c->pos, nullptr, c->orb_off, na, c->v, c->vorb));
+    HIPCHK(c, td::rowdot(st, c->rho_cur, 2 * np, c->H0, np, c->work1, np, np));
+    HIPCHK(c, td::energy_terms(st, c->work1, np, c->dq, c->v, c->pos, E, na, energy3));
+  }
+  HIPCHK(c, td::potential(st, c->gamma, c->dq, c->pos, E, c->orb_off, na, c->v, c->vorb));
+  HIPCHK(c, td::assemble_h(st, c->H0, c->S, c->vorb, c->H, np));
+  gemm(c, 1, np, np, np, 1.0, c->Sinv, np, c->H, np, c->A, np);
+  gemm(c, 2, np, 2 * np, np, 1.0, c->A, np, c->rho_cur, 2 * np, c->X, 2 * np);
+  HIPCHK(c, td::pair_sym(st, c->X, 2 * np, c->W, nullptr, np, np));
+  HIPCHK(c, td::ehrenfest_forces(st, c->rho_cur, 2 * np, c->W, c->GS, c->GH, c->vorb, c->orb_off,
+                                 c->dq, c->dgamma, E, na, c->n, np, c->F));
+}
+
+// One Ehrenfest step k (model matrices current at R_k): forces, velocity
+// Verlet around the leapfrog step of rho with the coupling D (Sec. 2.1,
+// Eqs. 10, 14, 15; Sec. 2.3, Eq. 19), then the matrices at R_{k+1}.
+void ehr_step(td_ctx* c, int k, const double* E) {
+  hipStream_t st = c->stream;
+  const int np = c->np, na = c->na;
+  const double dt = c->opt.dt;
+  ehr_forces(c, E, c->dip + 3 * (size_t)k, c->e_el + 3 * (size_t)k);
+  if (c->vel_half)
+    HIPCHK(c, td::kick_nuclei(st, c->vel, c->F, c->species, c->mass, na, 0.5 * dt));  // v_k
+  HIPCHK(c, td::kinetic_energy(st, c->vel, c->F, c->species, c->mass, na, 0.0, c->e_kin + k));
+  // X += -i S^-1 D rho with D from v_k
+  HIPCHK(c, td::nac_build(st, c->GS, c->vel, c->atom_of, c->n, np, c->Dm));
+  gemm(c, 0, np, np, np, 1.0, c->Sinv, np, c->Dm, np, c->A, np);
+  gemm(c, 0, np, 2 * np, np, 1.0, c->A, np, c->rho_cur, 2 * np, c->Z, 2 * np);
+  HIPCHK(c, td::add_minus_i(st, c->X, c->Z, np));
+  if (c->has_prev) {
+    HIPCHK(c, td::pair_leapfrog(st, c->X, c->X + np, 2 * np, c->rho_prev, c->rho_prev + np,
+                                2 * np, c->rho_prev, c->rho_prev + np, 2 * np, np, 2.0 * dt));
+  } else {
+    HIPCHK(c, td::pair_leapfrog(st, c->X, c->X + np, 2 * np, c->rho_cur, c->rho_cur + np,
+                                2 * np, c->rho_prev, c->rho_prev + np, 2 * np, np, dt));
+    c->has_prev = true;
+  }
+  std::swap(c->rho_cur, c->rho_prev);
+  HIPCHK(c, td::kick_nuclei(st, c->vel, c->F, c->species, c->mass, na, 0.5 * dt));  // v_{k+1/2}
+  HIPCHK(c, td::drift_nuclei(st, c->pos, c->vel, na, dt));
+  c->vel_half = true;
+  rebuild_model(c, true);
+}
+
 void step_impl(td_ctx* c, int nsteps, const double* field) {
   REQUIRE(c, nsteps >= 0, TD_EINVAL, "n must be >= 0");
   if (nsteps == 0) return;
@@ -596,6 +689,13 @@ void step_impl(td_ctx* c, int nsteps, const double* field) {
     c->dip = nullptr;
     c->dip_cap = 0;
     dalloc(c, &c->dip, 3 * (size_t)nsteps);
+    if (c->ehr) {
+      if (c->e_kin) hipFree(c->e_kin);
+      if (c->e_el) hipFree(c->e_el);
+      c->e_kin = c->e_el = nullptr;
+      dalloc(c, &c->e_kin, (size_t)nsteps);
+      dalloc(c, &c->e_el, 3 * (size_t)nsteps);
+    }
     c->dip_cap = nsteps;
   }
   if (field)
@@ -605,6 +705,17 @@ void step_impl(td_ctx* c, int nsteps, const double* field) {
   // events per step: start | G1 | G1 end | G2 | G2 end | update end
   if (prof) ensure_events(c, 6 * (size_t)nsteps);
   hipStream_t st = c->stream;
+  if (c->ehr) {
+    for (int k = 0; k < nsteps; ++k) {
+      ehr_step(c, k, field ? c->field + 3 * (size_t)k : nullptr);
+      c->step += 1;
+    }
+    c->last_n = nsteps;
+    HIPCHK(c, hipMemcpyAsync(c->pos_h.data(), c->pos, sizeof(double) * 3 * na,
+                             hipMemcpyDeviceToHost, st));
+    refresh(c);
+    return;
+  }
   for (int k = 0; k < nsteps; ++k) {
     hipEvent_t* e = prof ? &c->ev[6 * (size_t)k] : nullptr;
     if (prof) HIPCHK(c, hipEventRecord(e[0], st));
@@ -742,6 +853,153 @@ void split_gemm_host(td_ctx* c, int ns, int m, int n, int k, const double* A, co
   HIPCHK(c, hipMemcpy2DAsync(C, sizeof(double) * n, c->A, sizeof(double) * npd,
                              sizeof(double) * n, m, hipMemcpyDeviceToHost, c->stream));
   sync(c);
+}
+
+// Host checks of a two-centre model against the system's layout.
+void validate_model(td_ctx* c, const td_system* s, const td_model* m) {
+  REQUIRE(c, s && m, TD_EINVAL, "null system or model");
+  REQUIRE(c, s->n_atoms > 0 && s->n_orb > 0 && s->positions && s->orb_offset && s->q0,
+          TD_EINVAL, "null array in td_system");
+  REQUIRE(c, m->n_species > 0 && m->species && m->species_norb && m->sk_s && m->sk_h &&
+                 m->scale_s && m->scale_h && m->onsite && m->mass,
+          TD_EINVAL, "null array in td_model");
+  const int na = s->n_atoms, nsp = m->n_species;
+  for (int k = 0; k < nsp; ++k) {
+    REQUIRE(c, m->species_norb[k] == 1 || m->species_norb[k] == 4, TD_EINVAL,
+            "species_norb must be 1 or 4");
+    REQUIRE(c, m->mass[k] > 0 && std::isfinite(m->mass[k]), TD_EINVAL, "masses must be positive");
+  }
+  REQUIRE(c, s->orb_offset[0] == 0, TD_EINVAL, "orb_offset must start at 0");
+  for (int a = 0; a < na; ++a) {
+    REQUIRE(c, m->species[a] >= 0 && m->species[a] < nsp, TD_EINVAL, "species out of range");
+    REQUIRE(c, s->orb_offset[a + 1] - s->orb_offset[a] == m->species_norb[m->species[a]],
+            TD_EINVAL, "orb_offset does not match the species' orbital counts");
+  }
+  REQUIRE(c, s->orb_offset[na] == s->n_orb, TD_EINVAL, "orb_offset must end at n_orb");
+  REQUIRE(c, m->decay > 0 && std::isfinite(m->decay) && m->hubbard_u > 0 &&
+                 std::isfinite(m->hubbard_u),
+          TD_EINVAL, "decay and hubbard_u must be positive");
+  REQUIRE(c, finite_all(m->sk_s, (size_t)nsp * nsp * 4) && finite_all(m->sk_h, (size_t)nsp * nsp * 4) &&
+                 finite_all(m->onsite, (size_t)nsp * 2) &&
+                 finite_all(m->scale_s, (size_t)na * na) && finite_all(m->scale_h, (size_t)na * na) &&
+                 finite_all(s->positions, (size_t)na * 3),
+          TD_EINVAL, "non-finite model or positions");
+  for (int a = 0; a < na; ++a)
+    for (int b = a + 1; b < na; ++b) {
+      const double* p = s->positions;
+      const double d0 = p[3 * b] - p[3 * a], d1 = p[3 * b + 1] - p[3 * a + 1],
+                   d2 = p[3 * b + 2] - p[3 * a + 2];
+      REQUIRE(c, d0 * d0 + d1 * d1 + d2 * d2 > 1e-6, TD_EINVAL, "two atoms at one position");
+    }
+}
+
+// Model arrays, gradients and nuclear state on the device of context c.
+void upload_model(td_ctx* c, const td_system* s, const td_model* m, const double* vel) {
+  const int na = s->n_atoms, nsp = m->n_species, n = s->n_orb;
+  c->nsp = nsp;
+  c->decay = m->decay;
+  c->hub_u = m->hubbard_u;
+  ialloc(c, &c->species, na);
+  ialloc(c, &c->norb, nsp);
+  ialloc(c, &c->atom_of, c->np);
+  dalloc(c, &c->sk_s, (size_t)nsp * nsp * 4);
+  dalloc(c, &c->sk_h, (size_t)nsp * nsp * 4);
+  dalloc(c, &c->scale_s, (size_t)na * na);
+  dalloc(c, &c->scale_h, (size_t)na * na);
+  dalloc(c, &c->onsite, (size_t)nsp * 2);
+  dalloc(c, &c->mass, nsp);
+  dalloc(c, &c->GS, 3 * (size_t)c->np * c->np);
+  dalloc(c, &c->GH, 3 * (size_t)c->np * c->np);
+  dalloc(c, &c->dgamma, 3 * (size_t)na * na);
+  dalloc(c, &c->vel, 3 * (size_t)na);
+  dalloc(c, &c->F, 3 * (size_t)na);
+  std::vector<int> atom(c->np, 0);
+  for (int a = 0; a < na; ++a)
+    for (int u = s->orb_offset[a]; u < s->orb_offset[a + 1]; ++u) atom[u] = a;
+  (void)n;
+  hipStream_t st = c->stream;
+  HIPCHK(c, hipMemcpyAsync(c->species, m->species, sizeof(int) * na, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(c->norb, m->species_norb, sizeof(int) * nsp, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(c->atom_of, atom.data(), sizeof(int) * c->np, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(c->sk_s, m->sk_s, sizeof(double) * nsp * nsp * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(c->sk_h, m->sk_h, sizeof(double) * nsp * nsp * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(c->scale_s, m->scale_s, sizeof(double) * na * na, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(c->scale_h, m->scale_h, sizeof(double) * na * na, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(c->onsite, m->onsite, sizeof(double) * nsp * 2, hipMemcpyHostToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(c->mass, m->mass, sizeof(double) * nsp, hipMemcpyHostToDevice, st));
+  if (vel)
+    HIPCHK(c, hipMemcpyAsync(c->vel, vel, sizeof(double) * 3 * na, hipMemcpyHostToDevice, st));
+}
+
+void create_ehr_impl(td_ctx* c, const td_system* s, const td_model* m, const double* vel,
+                     const td_options* o) {
+  REQUIRE(c, o, TD_EINVAL, "null options");
+  REQUIRE(c, s && (s->flags & TD_DEVICE_PTRS) == 0, TD_EINVAL,
+          "moving-nuclei contexts take host pointers");
+  validate_model(c, s, m);
+  REQUIRE(c, o->precision == TD_FP64, TD_ENOTSUP, "moving nuclei run in TD_FP64 precision only");
+  if (vel) REQUIRE(c, finite_all(vel, 3 * (size_t)s->n_atoms), TD_EINVAL, "non-finite velocities");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  REQUIRE(c, e == hipSuccess && ndev > 0, TD_EHIP,
+          std::string("no HIP device available: ") + hipGetErrorString(e));
+  // S, H0 and gamma at the initial positions, built on the device
+  const int na = s->n_atoms, n = s->n_orb;
+  std::vector<double> hS((size_t)n * n), hH((size_t)n * n), hG((size_t)na * na);
+  {
+    td_ctx b;
+    b.na = na;
+    b.n = n;
+    b.np = round_up(n, td::kPad);
+    struct Free {
+      td_ctx* p;
+      ~Free() {
+        if (p->stream) hipStreamSynchronize(p->stream);
+        free_all(p);
+      }
+    } guard{&b};
+    try {
+      HIPCHK(&b, hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking));
+      b.own_stream = true;
+      const size_t m2 = (size_t)b.np * b.np;
+      dalloc(&b, &b.S, m2);
+      dalloc(&b, &b.H0, m2);
+      dalloc(&b, &b.gamma, (size_t)na * na);
+      dalloc(&b, &b.pos, 3 * (size_t)na);
+      HIPCHK(&b, hipMalloc((void**)&b.orb_off, sizeof(int) * (na + 1)));
+      HIPCHK(&b, hipMemcpyAsync(b.orb_off, s->orb_offset, sizeof(int) * (na + 1),
+                                hipMemcpyHostToDevice, b.stream));
+      HIPCHK(&b, hipMemcpyAsync(b.pos, s->positions, sizeof(double) * 3 * na,
+                                hipMemcpyHostToDevice, b.stream));
+      upload_model(&b, s, m, nullptr);
+      HIPCHK(&b, td::model_build(b.stream, model_args(&b), b.pos, b.S, b.H0, b.GS, b.GH, b.np));
+      HIPCHK(&b, td::gamma_build(b.stream, b.pos, na, b.hub_u, b.gamma, b.dgamma));
+      HIPCHK(&b, hipMemcpy2DAsync(hS.data(), sizeof(double) * n, b.S, sizeof(double) * b.np,
+                                  sizeof(double) * n, n, hipMemcpyDeviceToHost, b.stream));
+      HIPCHK(&b, hipMemcpy2DAsync(hH.data(), sizeof(double) * n, b.H0, sizeof(double) * b.np,
+                                  sizeof(double) * n, n, hipMemcpyDeviceToHost, b.stream));
+      HIPCHK(&b, hipMemcpyAsync(hG.data(), b.gamma, sizeof(double) * na * na,
+                                hipMemcpyDeviceToHost, b.stream));
+      HIPCHK(&b, hipStreamSynchronize(b.stream));
+    } catch (const Fail& f) {
+      c->err = b.err;
+      throw;
+    }
+  }
+  td_system view = *s;
+  view.S = hS.data();
+  view.H0 = hH.data();
+  view.gamma = hG.data();
+  create_impl(c, &view, o);
+  upload_model(c, s, m, vel);
+  const size_t m2 = (size_t)c->np * c->np;
+  dalloc(c, &c->W, m2);
+  dalloc(c, &c->Dm, m2);
+  dalloc(c, &c->Z, 2 * m2);
+  c->ehr = true;
+  c->vel_half = false;
+  rebuild_model(c, true);
+  refresh(c);
 }
 
 }  // namespace
@@ -931,10 +1189,77 @@ td_status td_reset_kernel_time(td_ctx* ctx) {
 }
 
 td_status td_get_forces(td_ctx* ctx, double* forces) {
-  (void)forces;
-  if (!ctx) return TD_EINVAL;
-  ctx->err = "forces need moving nuclei (Ehrenfest dynamics), which this build does not run";
-  return TD_ENOTSUP;
+  return guarded(ctx, [&] {
+    td_ctx* c = ctx;
+    REQUIRE(c, c->ehr, TD_ENOTSUP,
+            "forces need a model of S(R) and H0(R): create the context with "
+            "td_create_ehrenfest");
+    REQUIRE(c, forces, TD_EINVAL, "null output");
+    ehr_forces(c, nullptr, c->scal + SC_MU, nullptr);
+    HIPCHK(c, hipMemcpyAsync(forces, c->F, sizeof(double) * 3 * c->na, hipMemcpyDeviceToHost,
+                             c->stream));
+    sync(c);
+  });
+}
+
+td_status td_create_ehrenfest(const td_system* sys, const td_model* model,
+                              const double* velocities, const td_options* opt, td_ctx** out,
+                              char* err, int32_t errlen) {
+  if (!out) {
+    set_err(err, errlen, "out must not be null");
+    return TD_EINVAL;
+  }
+  *out = nullptr;
+  td_ctx* c = new (std::nothrow) td_ctx();
+  if (!c) {
+    set_err(err, errlen, "host allocation failed");
+    return TD_ENOMEM;
+  }
+  td_status st = guarded(c, [&] { create_ehr_impl(c, sys, model, velocities, opt); });
+  if (st != TD_OK) {
+    set_err(err, errlen, c->err);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+    return st;
+  }
+  set_err(err, errlen, "");
+  *out = c;
+  return TD_OK;
+}
+
+td_status td_get_nuclei(td_ctx* ctx, double* positions, double* velocities) {
+  return guarded(ctx, [&] {
+    td_ctx* c = ctx;
+    REQUIRE(c, c->ehr, TD_ENOTSUP, "clamped-nuclei context");
+    if (positions)
+      HIPCHK(c, hipMemcpyAsync(positions, c->pos, sizeof(double) * 3 * c->na,
+                               hipMemcpyDeviceToHost, c->stream));
+    if (velocities)
+      HIPCHK(c, hipMemcpyAsync(velocities, c->vel, sizeof(double) * 3 * c->na,
+                               hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+  });
+}
+
+td_status td_get_energy_series(td_ctx* ctx, double* e_el, double* e_kin, int32_t cap,
+                               int32_t* n_out) {
+  return guarded(ctx, [&] {
+    td_ctx* c = ctx;
+    REQUIRE(c, c->ehr, TD_ENOTSUP, "clamped-nuclei context");
+    REQUIRE(c, n_out && cap >= 0 && ((e_el && e_kin) || cap == 0), TD_EINVAL, "invalid output");
+    const int k = std::min(cap, c->last_n);
+    std::vector<double> parts(3 * (size_t)std::max(k, 1));
+    if (k > 0) {
+      HIPCHK(c, hipMemcpyAsync(parts.data(), c->e_el, sizeof(double) * 3 * k,
+                               hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipMemcpyAsync(e_kin, c->e_kin, sizeof(double) * k, hipMemcpyDeviceToHost,
+                               c->stream));
+    }
+    sync(c);
+    for (int i = 0; i < k; ++i) e_el[i] = parts[3 * i] + parts[3 * i + 1] + parts[3 * i + 2];
+    *n_out = c->last_n;
+  });
 }
 
 const char* td_last_error(const td_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }

@@ -29,7 +29,8 @@ EXPORTED = [
     "td_last_error", "td_status_string", "td_destroy", "td_util_gemm",
     "td_batch_create", "td_batch_kick", "td_batch_step", "td_batch_get_dipole_series",
     "td_batch_get_charges", "td_batch_get_rho", "td_batch_get_info", "td_batch_last_error",
-    "td_batch_destroy", "td_spectrum", "td_transient_absorption",
+    "td_batch_destroy", "td_spectrum", "td_transient_absorption", "td_create_ehrenfest",
+    "td_get_nuclei", "td_get_energy_series",
 ]
 TD_BATCH_NO_GRAPH, TD_BATCH_TILE_128, TD_BATCH_TILE_64 = 1, 2, 4
 TD_BATCH_BUCKETS = 8
@@ -122,6 +123,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "td_batch_get_info": (ctypes.c_int32, [vp, ctypes.POINTER(TdBatchInfo)]),
         "td_batch_last_error": (ctypes.c_char_p, [vp]),
         "td_batch_destroy": (None, [vp]),
+        "td_create_ehrenfest": (ctypes.c_int32, [ctypes.POINTER(TdSystem), ctypes.POINTER(TdModel),
+                                                 _dp, ctypes.POINTER(TdOptions),
+                                                 ctypes.POINTER(vp), ctypes.c_char_p,
+                                                 ctypes.c_int32]),
+        "td_get_nuclei": (ctypes.c_int32, [vp, _dp, _dp]),
+        "td_get_energy_series": (ctypes.c_int32, [vp, _dp, _dp, ctypes.c_int32, _ip]),
         "td_spectrum": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_int32, _dp,
                                          _dp, _dp, _dp, ctypes.c_char_p, ctypes.c_int32]),
@@ -159,6 +166,13 @@ def td_default_options() -> TdOptions:
     o = TdOptions()
     load().td_default_options(ctypes.byref(o))
     return o
+
+
+class TdModel(ctypes.Structure):
+    _fields_ = [("n_species", ctypes.c_int32), ("species", _ip), ("species_norb", _ip),
+                ("sk_s", _dp), ("sk_h", _dp), ("decay", ctypes.c_double), ("scale_s", _dp),
+                ("scale_h", _dp), ("onsite", _dp), ("hubbard_u", ctypes.c_double),
+                ("mass", _dp)]
 
 
 class TdBatchInfo(ctypes.Structure):
@@ -241,6 +255,51 @@ def td_create(system, options: Optional[TdOptions] = None, rho0: Optional[np.nda
               occ: Optional[np.ndarray] = None):
     """td_create: returns an opaque context handle (c_void_p)."""
     return _create(_host_system(system, rho0, occ), options)
+
+
+def td_create_ehrenfest(system, model: dict, velocities=None, options: Optional[TdOptions] = None,
+                        rho0: Optional[np.ndarray] = None):
+    """td_create_ehrenfest over host arrays; ``model`` as workloads.two_centre_model."""
+    hs = _host_system(system, rho0)
+    keep = _Keep()
+    keep.species = np.ascontiguousarray(model["species"], dtype=np.int32)
+    keep.norb = np.ascontiguousarray(model["species_norb"], dtype=np.int32)
+    keep.sk_s = _f64(model["sk_s"])
+    keep.sk_h = _f64(model["sk_h"])
+    keep.scale_s = _f64(model["scale_s"])
+    keep.scale_h = _f64(model["scale_h"])
+    keep.onsite = _f64(model["onsite"])
+    keep.mass = _f64(model["mass"])
+    keep.vel = None if velocities is None else _f64(velocities)
+    m = TdModel(n_species=len(keep.norb), species=_ptr(keep.species, np.int32),
+                species_norb=_ptr(keep.norb, np.int32), sk_s=_ptr(keep.sk_s),
+                sk_h=_ptr(keep.sk_h), decay=float(model["decay"]), scale_s=_ptr(keep.scale_s),
+                scale_h=_ptr(keep.scale_h), onsite=_ptr(keep.onsite),
+                hubbard_u=float(model["hubbard_u"]), mass=_ptr(keep.mass))
+    opt = options if options is not None else td_default_options()
+    ctx = ctypes.c_void_p()
+    err = ctypes.create_string_buffer(1024)
+    st = load().td_create_ehrenfest(ctypes.byref(hs), ctypes.byref(m), _ptr(keep.vel),
+                                    ctypes.byref(opt), ctypes.byref(ctx), err, 1024)
+    if st != TD_OK:
+        raise TdError(st, err.value.decode())
+    return ctx
+
+
+def td_get_nuclei(ctx, n_atoms: int):
+    pos = np.empty((n_atoms, 3))
+    vel = np.empty((n_atoms, 3))
+    _check(ctx, load().td_get_nuclei(ctx, _ptr(pos), _ptr(vel)))
+    return pos, vel
+
+
+def td_get_energy_series(ctx, cap: int):
+    ee = np.empty(max(cap, 1))
+    ek = np.empty(max(cap, 1))
+    n = ctypes.c_int32()
+    _check(ctx, load().td_get_energy_series(ctx, _ptr(ee), _ptr(ek), int(cap), ctypes.byref(n)))
+    k = min(cap, n.value)
+    return ee[:k], ek[:k]
 
 
 def _bcheck(b, st):
@@ -564,3 +623,27 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Ehrenfest(Propagator):
+    """One trajectory with moving nuclei (td_create_ehrenfest)."""
+
+    def __init__(self, system, model, velocities=None, dt=0.2, rho0=None, scc_tol=1e-12,
+                 scc_maxiter=300):
+        opt = td_default_options()
+        opt.dt = dt
+        opt.scc_tol = scc_tol
+        opt.scc_maxiter = scc_maxiter
+        self.n_atoms = len(system.q0)
+        self.n_orb = int(system.orb_offset[-1])
+        self.ctx = td_create_ehrenfest(system, model, velocities, opt, rho0=rho0)
+
+    def forces(self):
+        return td_get_forces(self.ctx, self.n_atoms)
+
+    def nuclei(self):
+        return td_get_nuclei(self.ctx, self.n_atoms)
+
+    def energy_series(self, n):
+        return td_get_energy_series(self.ctx, n)
+

@@ -140,3 +140,19 @@ def test_spectrum_arguments_rejected_before_device(T):
         T.td_transient_absorption(np.zeros((3, 2, 10)), np.zeros((3, 2, 10)), 1e-3, 0.2, [0.1],
                                   ref_delay=5)
     assert e.value.status == T.TD_EINVAL
+
+
+def test_ehrenfest_arguments_rejected_before_device(T):
+    s = W.benzene()
+    m = W.two_centre_model(s)
+    o = T.td_default_options()
+    o.precision = T.TD_SPLIT_BF16
+    with pytest.raises(T.TdError) as e:
+        T.td_create_ehrenfest(s, m, None, o)
+    assert e.value.status == T.TD_ENOTSUP
+    with pytest.raises(T.TdError) as e:
+        T.td_create_ehrenfest(s, dict(m, decay=-1.0))
+    assert e.value.status == T.TD_EINVAL
+    with pytest.raises(T.TdError) as e:
+        T.td_create_ehrenfest(s, dict(m, species=np.zeros(s.n_atoms, dtype=np.int32)))
+    assert e.value.status == T.TD_EINVAL

@@ -1,0 +1,117 @@
+"""Moving nuclei (Ehrenfest) on the GPU against the CPU oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.ehrenfest as OE
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _T():
+    from paper_1912_03174_amd import tddftb as T
+    return T
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_forces(s, m, rho, field=None):
+    S, H0 = OE.model_matrices(m, s.positions)
+    gamma = OE.gamma_matrix(s.positions, m["hubbard_u"])
+    Sinv = O.inverse_overlap(S)
+    GS, GH = OE.fd_gradients(m, s.positions)
+    atom_of, _ = OE.orbital_types(m)
+    dq = O.charge_fluctuations(rho, S, s.orb_offset, s.q0)
+    vx = np.zeros(s.n_atoms) if field is None else O.external_potential(s.positions, field)
+    v_orb = (gamma @ dq + vx)[atom_of]
+    H = H0 + 0.5 * S * (v_orb[:, None] + v_orb[None, :])
+    return OE.forces(rho, H, Sinv, GS, GH, v_orb, dq, s.positions, m["hubbard_u"], field, m)
+
+
+@pytest.mark.parametrize("which", ["benzene", "flake"])
+def test_ground_state_forces_match_oracle(which):
+    T = _T()
+    s = W.benzene() if which == "benzene" else W.flake_c24h16()
+    m = W.two_centre_model(s)
+    say(f"forces {which}")
+    gs = O.ground_state(s, tol=1e-13)
+    e = T.Ehrenfest(s, m, rho0=gs.rho)
+    F = e.forces()
+    ref = oracle_forces(s, m, gs.rho)
+    err = np.abs(F - ref).max() / np.abs(ref).max()
+    say(f"force relative difference {err:.2e}")
+    assert err < 1e-9
+    pos, vel = e.nuclei()
+    assert np.array_equal(pos, s.positions) and np.all(vel == 0.0)
+    e.close()
+
+
+def test_trajectory_matches_oracle():
+    T = _T()
+    s = W.benzene()
+    m = W.two_centre_model(s)
+    say("ehrenfest trajectory benzene")
+    gs = O.ground_state(s, tol=1e-13)
+    Sinv = O.inverse_overlap(s.S)
+    vel = W.thermal_velocities(s, 1500.0, seed=9)
+    n = 150
+    field = W.sin2_pulse(np.arange(n) * 0.2, 0.01, 0.4, n * 0.2, (1.0, 0.5, 0.2))
+    e = T.Ehrenfest(s, m, velocities=vel, rho0=gs.rho)
+    e.kick(1e-3, (0.0, 1.0, 0.0))
+    mu = e.step(n, field)
+    ee, ek = e.energy_series(n)
+    pos, _ = e.nuclei()
+    rho = e.rho()[0]
+    rk = O.kick(gs.rho, s.S, Sinv, s.positions, s.orb_offset, 1e-3, (0.0, 1.0, 0.0))
+    ref = OE.propagate(s, m, rk, vel, n, 0.2, field=field)
+    d_err = np.abs(mu - ref.dipoles).max() / np.abs(ref.dipoles - ref.dipoles[0]).max()
+    say(f"dipole relative difference {d_err:.2e}")
+    assert d_err < 1e-8
+    assert np.abs(pos - ref.positions).max() < 1e-10
+    assert np.abs(ek - ref.e_kin).max() < 1e-10 * ref.e_kin.max()
+    assert np.abs(ee - ref.e_elec).max() < 1e-10 * np.abs(ref.e_elec).max()
+    assert np.abs(rho - ref.rho).max() < 1e-10
+    e.close()
+
+
+def test_energy_conserved_on_gpu():
+    T = _T()
+    s = W.flake_c24h16()
+    m = W.two_centre_model(s)
+    say("ehrenfest energy conservation flake")
+    e = T.Ehrenfest(s, m, velocities=W.thermal_velocities(s, 2000.0, seed=4), scc_tol=1e-12)
+    e.kick(5e-3, (1.0, 0.0, 0.0))
+    n = 400
+    e.step(n)
+    ee, ek = e.energy_series(n)
+    tot = ee + ek
+    swing = np.abs(ek - ek[0]).max()
+    say(f"kinetic swing {swing:.3e}, total drift {np.abs(tot - tot[0]).max():.3e}")
+    assert swing > 1e-2 and np.abs(tot - tot[0]).max() < 2e-3 * swing
+    e.close()
+
+
+def test_ehrenfest_errors():
+    T = _T()
+    s = W.benzene()
+    m = W.two_centre_model(s)
+    o = T.td_default_options()
+    o.precision = T.TD_SPLIT_BF16
+    with pytest.raises(T.TdError) as err:
+        T.td_create_ehrenfest(s, m, None, o)
+    assert err.value.status == T.TD_ENOTSUP
+    bad = dict(m, species_norb=np.array([4, 4], dtype=np.int32))
+    with pytest.raises(T.TdError) as err:
+        T.td_create_ehrenfest(s, bad)
+    assert err.value.status == T.TD_EINVAL
+    p = T.Propagator(s)
+    with pytest.raises(T.TdError) as err:
+        T.td_get_nuclei(p.ctx, s.n_atoms)
+    assert err.value.status == T.TD_ENOTSUP
+    p.close()
