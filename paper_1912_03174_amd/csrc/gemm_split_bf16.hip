@@ -171,11 +171,16 @@ __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
   const int in_g = lin - g * group;
   const int m0 = (first_m + in_g % gsz) * BM;
   // When the columns below n_split (K = k_hi) and above it (K = k_lo) are
-  // two equal halves, column tiles alternate between the halves, so every
-  // XCD's contiguous range of tiles holds as much long-K as short-K work.
+  // two equal halves, runs of `run` column tiles alternate between the
+  // halves, so every XCD's contiguous range of tiles holds as much long-K as
+  // short-K work while neighbouring tiles still share K positions (L2 reuse).
   const int ci = in_g / gsz;
+  const int half = p.tiles_n / 2;
   const bool alternate = p.k_lo != p.k_hi && 2 * p.n_split == p.tiles_n * BN;
-  const int n0 = (alternate ? ((ci & 1) ? p.tiles_n / 2 + (ci >> 1) : (ci >> 1)) : ci) * BN;
+  int run = 16;
+  while (run > 1 && half % run) run >>= 1;
+  const int chunk = ci / run;
+  const int n0 = (alternate ? ((chunk & 1) * half + (chunk >> 1) * run + ci % run) : ci) * BN;
   const int K = (n0 < p.n_split) ? p.k_hi : p.k_lo;
   const int nk = K / BK;
 
@@ -426,24 +431,48 @@ hipError_t launch_split(hipStream_t st, const SplitGemm& g) {
 // Same slicing for rows of at most 128 CPL values, two waves per row: each
 // lane keeps its CPL values in registers between the row maximum and the
 // slicing, so the source is read from memory once instead of twice.
+// SLICE_SUM_AND_M1 slices two rows (M0 + M1 and M1) from one read of M1.
+template <int S>
+__device__ __forceinline__ void slice_store(double x, int e, __bf16* o) {
+  double rr = ldexp(x, 8 - e);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const double sig = rint(rr);
+    o[s * 16] = (__bf16)(float)ldexp(sig, -8 * s);
+    rr = (rr - sig) * 256.0;
+  }
+}
+
+__device__ __forceinline__ double pair_max(double m, double* wmax) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  return fmax(wmax[(threadIdx.x >> 7) * 2], wmax[(threadIdx.x >> 7) * 2 + 1]);
+}
+
 template <int S, int MODE, int CPL>
 __global__ __launch_bounds__(256) void k_slice_rows_cached(SliceSrc src, int rows, int cols,
                                                            __bf16* out, int ldo, int* exps) {
-  __shared__ double wmax[4];
+  __shared__ double wmax[4], wmax2[4];
   const int row = blockIdx.x * 2 + (threadIdx.x >> 7);
   const int l = threadIdx.x & 127;
   const bool live = row < rows;
-  double x[CPL];
-  double m = 0.0;
+  constexpr bool TWO = MODE == SLICE_SUM_AND_M1;
+  double x[CPL], y[TWO ? CPL : 1];
+  double m = 0.0, m2 = 0.0;
 #pragma unroll
   for (int j = 0; j < CPL; ++j) {
     const int c = l + 128 * j;
-    double val = 0.0;
+    double val = 0.0, val2 = 0.0;
     if (live && c < cols) {
       if (MODE == SLICE_PLAIN) {
         val = src.sign * src.M0[(size_t)row * src.ld0 + c];
       } else if (MODE == SLICE_SUM) {
         val = src.M0[(size_t)row * src.ld0 + c] + src.M1[(size_t)row * src.ld1 + c];
+      } else if (MODE == SLICE_SUM_AND_M1) {
+        val2 = src.M1[(size_t)row * src.ld1 + c];
+        val = src.M0[(size_t)row * src.ld0 + c] + val2;
       } else if (MODE == SLICE_RENORM) {
         val = src.M0[(size_t)row * src.ld0 + c] - src.cs[0] * src.M1[(size_t)row * src.ld1 + c];
       } else {
@@ -452,29 +481,29 @@ __global__ __launch_bounds__(256) void k_slice_rows_cached(SliceSrc src, int row
     }
     x[j] = val;
     m = fmax(m, fabs(val));
+    if constexpr (TWO) {
+      y[j] = val2;
+      m2 = fmax(m2, fabs(val2));
+    }
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
-  __syncthreads();
-  m = fmax(wmax[(threadIdx.x >> 7) * 2], wmax[(threadIdx.x >> 7) * 2 + 1]);
+  m = pair_max(m, wmax);
+  if constexpr (TWO) m2 = pair_max(m2, wmax2);
   if (!live) return;
-  int e = 0;
+  int e = 0, e2 = 0;
   if (m > 0.0) frexp(m, &e);
-  if (l == 0) exps[row] = e;
+  if (TWO && m2 > 0.0) frexp(m2, &e2);
+  if (l == 0) {
+    exps[row] = e;
+    if (TWO) src.exps2[row] = e2;
+  }
 #pragma unroll
   for (int j = 0; j < CPL; ++j) {
     const int c = l + 128 * j;
     if (c < cols) {
       if (MODE == SLICE_RENORM) src.M0w[(size_t)row * src.ld0 + c] = x[j];
-      double rr = ldexp(x[j], 8 - e);
-      __bf16* o = out + (size_t)row * ldo + (size_t)(c >> 4) * (16 * S) + (c & 15);
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const double sig = rint(rr);
-        o[s * 16] = (__bf16)(float)ldexp(sig, -8 * s);
-        rr = (rr - sig) * 256.0;
-      }
+      const size_t at = (size_t)row * ldo + (size_t)(c >> 4) * (16 * S) + (c & 15);
+      slice_store<S>(x[j], e, out + at);
+      if constexpr (TWO) slice_store<S>(y[j], e2, src.out2 + at);
     }
   }
 }
@@ -500,6 +529,11 @@ hipError_t launch_slice(hipStream_t st, int mode, const SliceSrc& src, int rows,
       case SLICE_RENORM:
         hipLaunchKernelGGL((k_slice_rows_cached<S, SLICE_RENORM, 32>), grid, block, 0, st, src,
                            rows, cols, out, ldo, exps);
+        break;
+      case SLICE_SUM_AND_M1:
+        if (!src.out2 || !src.exps2) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_slice_rows_cached<S, SLICE_SUM_AND_M1, 32>), grid, block, 0, st,
+                           src, rows, cols, out, ldo, exps);
         break;
       default:
         return hipErrorInvalidValue;

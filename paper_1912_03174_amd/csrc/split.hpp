@@ -5,13 +5,16 @@
 
 namespace td {
 
-enum { SLICE_PLAIN = 0, SLICE_SUM = 1, SLICE_DH = 2, SLICE_RENORM = 3 };
+enum { SLICE_PLAIN = 0, SLICE_SUM = 1, SLICE_DH = 2, SLICE_RENORM = 3, SLICE_SUM_AND_M1 = 4 };
 
 // Source of the values sliced row by row:
 //   SLICE_PLAIN: sign * M0[r][c]
 //   SLICE_SUM:   M0[r][c] + M1[r][c]
 //   SLICE_DH:    1/2 M0[r][c] (v[r] + v[c])   (M0 = S, v = potential change)
 //   SLICE_RENORM: M0[r][c] - cs[0] M1[r][c], also written back to M0
+//   SLICE_SUM_AND_M1: M0 + M1 into out / exps and, in the same pass, M1 into
+//                     out2 / exps2 (one read of M1 for both); rows of at most
+//                     4096 values
 struct SliceSrc {
   const double* M0 = nullptr;
   int ld0 = 0;
@@ -21,6 +24,8 @@ struct SliceSrc {
   double sign = 1.0;
   const double* cs = nullptr;
   double* M0w = nullptr;   // SLICE_RENORM: writable alias of M0
+  __bf16* out2 = nullptr;  // SLICE_SUM_AND_M1: second output (same ldo)
+  int* exps2 = nullptr;
 };
 
 // C[m x n] = sum over K segments of 2^(eL+fR-16) (sliced L)(sliced R)^T (+ Cin).

@@ -401,11 +401,18 @@ void split_products(td_ctx* c, const double* E, hipEvent_t* ev) {
   sa.ld0 = np;
   sa.M1 = c->H;
   sa.ld1 = np;
-  slice(c, td::SLICE_SUM, sa, np, np, c->sl_L2, 2 * np * S, c->e_L2);
-  td::SliceSrc sb;
-  sb.M0 = c->H;
-  sb.ld0 = np;
-  slice(c, td::SLICE_PLAIN, sb, np, np, c->sl_L2 + (size_t)np * S, 2 * np * S, c->e_L2 + np);
+  if (np <= 4096) {
+    // [A_ref + B | B] from one read of B
+    sa.out2 = c->sl_L2 + (size_t)np * S;
+    sa.exps2 = c->e_L2 + np;
+    slice(c, td::SLICE_SUM_AND_M1, sa, np, np, c->sl_L2, 2 * np * S, c->e_L2);
+  } else {
+    slice(c, td::SLICE_SUM, sa, np, np, c->sl_L2, 2 * np * S, c->e_L2);
+    td::SliceSrc sb;
+    sb.M0 = c->H;
+    sb.ld0 = np;
+    slice(c, td::SLICE_PLAIN, sb, np, np, c->sl_L2 + (size_t)np * S, 2 * np * S, c->e_L2 + np);
+  }
   td::SliceSrc sdr;
   sdr.M0 = c->rho_cur;
   sdr.M0w = c->rho_cur;

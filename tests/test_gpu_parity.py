@@ -287,13 +287,15 @@ def strip4096():
     return W.workload(3)
 
 
-def test_full_size_one_step_sampled_rows(strip4096):
-    """N_orb = 4096 in the benchmark's launch configuration: rows of one leapfrog step."""
+@pytest.mark.parametrize("cfg", [3, 2])
+def test_full_size_one_step_sampled_rows(cfg, strip4096):
+    """N_orb = 4096 in the benchmark's launch configuration (and the 2944-orbital
+    strip): rows of one leapfrog step."""
     T = _T()
-    w = strip4096
+    w = strip4096 if cfg == 3 else W.workload(2)
     s = w.system
     n = s.n_orb
-    say("full size 4096 sampled rows")
+    say(f"full size {n} sampled rows")
     # seeded Hermitian densities around the neutral rho = 1 (inputs, not physics)
     r1, i1 = W.random_hermitian_pair(n, seed=41, scale=1e-3, base=np.eye(n))
     r0, i0 = W.random_hermitian_pair(n, seed=42, scale=1e-3, base=np.eye(n))
