@@ -9,8 +9,9 @@
 // (rows, atoms, product tiles, tile pairs). The two density buffers of each
 // member alternate roles step by step, so the steps after the Euler start
 // are two fixed launch sequences (even and odd parity), captured once as
-// HIP graphs and replayed; a device step counter indexes the field and the
-// dipole record, so the graphs need no per-step arguments.
+// HIP graphs (one step, and runs of 16 steps) and replayed; a device step
+// counter indexes the field and the dipole record, so the graphs need no
+// per-step arguments.
 //
 // Product tiles: members are grouped in size buckets (padded n / 128); a
 // bucket's products run as 128 x 128 or 64 x 64 tiles, chosen by timing
@@ -66,12 +67,17 @@ struct td_batch {
   double* dip = nullptr;
   int* kstep = nullptr;
   int cap = 0;
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t graph[2] = {nullptr, nullptr};       // one leapfrog step, by parity
+  hipGraphExec_t graph_run[2] = {nullptr, nullptr};   // kGraphRun steps, by parity
 };
 
 namespace {
 
 constexpr int kTiles[2] = {128, 64};
+// Steps captured in one graph for long runs: one graph launch costs tens of
+// microseconds, about a whole small-batch step, so runs of steps share it.
+// Even, so a run returns the density buffers to the parity it started from.
+constexpr int kGraphRun = 16;
 
 template <class T>
 void upload(td_batch* b, T** dst, const std::vector<T>& src) {
@@ -84,10 +90,11 @@ void upload(td_batch* b, T** dst, const std::vector<T>& src) {
 }
 
 void drop_graphs(td_batch* b) {
-  for (hipGraphExec_t& g : b->graph) {
-    if (g) hipGraphExecDestroy(g);
-    g = nullptr;
-  }
+  for (hipGraphExec_t* set : {b->graph, b->graph_run})
+    for (int p = 0; p < 2; ++p) {
+      if (set[p]) hipGraphExecDestroy(set[p]);
+      set[p] = nullptr;
+    }
 }
 
 // Problems of the two products of member m for tile edge T and parity p.
@@ -217,18 +224,19 @@ void step_body(td_batch* b, int cur, bool euler) {
   HIPCHK(b, td::batch_tick(s, b->kstep, 0));
 }
 
-void capture(td_batch* b, int cur) {
+// Captures `steps` leapfrog steps starting from parity `cur` into *out.
+void capture(td_batch* b, int cur, int steps, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   HIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   try {
-    step_body(b, cur, false);
+    for (int k = 0; k < steps; ++k) step_body(b, cur ^ (k & 1), false);
   } catch (...) {
     hipStreamEndCapture(b->stream, &g);
     if (g) hipGraphDestroy(g);
     throw;
   }
   HIPCHK(b, hipStreamEndCapture(b->stream, &g));
-  hipError_t e = hipGraphInstantiate(&b->graph[cur], g, nullptr, nullptr, 0);
+  hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   HIPCHK(b, e);
 }
@@ -383,18 +391,25 @@ void step_impl(td_batch* b, int n, const double* field) {
   HIPCHK(b, td::batch_tick(b->stream, b->kstep, 1));
   const bool use_graph = !(b->flags & TD_BATCH_NO_GRAPH);
   b->last_n = 0;
-  for (int k = 0; k < n; ++k) {
+  for (int k = 0; k < n;) {
     if (!b->has_prev) {
       step_body(b, b->parity, true);
       b->has_prev = true;
+    } else if (use_graph && n - k >= kGraphRun) {
+      if (!b->graph_run[b->parity]) capture(b, b->parity, kGraphRun, &b->graph_run[b->parity]);
+      HIPCHK(b, hipGraphLaunch(b->graph_run[b->parity], b->stream));
+      b->step += kGraphRun;        // even: the parity is unchanged
+      k += kGraphRun;
+      continue;
     } else if (use_graph) {
-      if (!b->graph[b->parity]) capture(b, b->parity);
+      if (!b->graph[b->parity]) capture(b, b->parity, 1, &b->graph[b->parity]);
       HIPCHK(b, hipGraphLaunch(b->graph[b->parity], b->stream));
     } else {
       step_body(b, b->parity, false);
     }
     b->parity ^= 1;
     b->step += 1;
+    ++k;
   }
   b->last_n = n;
   sync_members(b);
