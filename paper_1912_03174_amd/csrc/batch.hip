@@ -92,7 +92,7 @@ void upload(td_batch* b, T** dst, const std::vector<T>& src) {
 void drop_graphs(td_batch* b) {
   for (hipGraphExec_t* set : {b->graph, b->graph_run})
     for (int p = 0; p < 2; ++p) {
-      if (set[p]) hipGraphExecDestroy(set[p]);
+      if (set[p]) (void)hipGraphExecDestroy(set[p]);
       set[p] = nullptr;
     }
 }
@@ -167,15 +167,15 @@ void tune_tiles(td_batch* b) {
   struct Ev {
     hipEvent_t a, b;
     ~Ev() {
-      hipEventDestroy(a);
-      hipEventDestroy(b);
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
     }
   } guard{e0, e1};
   td::GemmProblem* tmp = nullptr;
   struct Tmp {
     td::GemmProblem** p;
     ~Tmp() {
-      if (*p) hipFree(*p);
+      if (*p) (void)hipFree(*p);
     }
   } tguard{&tmp};
   for (int k = 0; k < TD_BATCH_BUCKETS; ++k) {
@@ -231,13 +231,13 @@ void capture(td_batch* b, int cur, int steps, hipGraphExec_t* out) {
   try {
     for (int k = 0; k < steps; ++k) step_body(b, cur ^ (k & 1), false);
   } catch (...) {
-    hipStreamEndCapture(b->stream, &g);
-    if (g) hipGraphDestroy(g);
+    (void)hipStreamEndCapture(b->stream, &g);
+    if (g) (void)hipGraphDestroy(g);
     throw;
   }
   HIPCHK(b, hipStreamEndCapture(b->stream, &g));
   hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   HIPCHK(b, e);
 }
 
@@ -267,16 +267,16 @@ void refresh_members(td_batch* b) {
 }
 
 void free_batch(td_batch* b) {
-  if (b->stream) hipStreamSynchronize(b->stream);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
   drop_graphs(b);
   void* bufs[] = {b->mem_d, b->rows_d, b->atoms_d, b->pairs_d, b->g1_d[0], b->g1_d[1],
                   b->g2_d[0][0], b->g2_d[0][1], b->g2_d[1][0], b->g2_d[1][1], b->field,
                   b->dip, b->kstep};
   for (void* p : bufs)
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   for (td_ctx* c : b->mem) td_destroy(c);
   b->mem.clear();
-  if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   b->stream = nullptr;
 }
 

@@ -35,9 +35,9 @@ struct SpecRun {
   hipStream_t stream = nullptr;
   std::vector<void*> bufs;
   ~SpecRun() {
-    if (stream) hipStreamSynchronize(stream);
-    for (void* p : bufs) hipFree(p);
-    if (stream) hipStreamDestroy(stream);
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void* p : bufs) (void)hipFree(p);
+    if (stream) (void)hipStreamDestroy(stream);
   }
   double* alloc(size_t count) {
     void* p = nullptr;

@@ -47,42 +47,42 @@ void free_all(td_ctx* c) {
                      &c->dq,  &c->dq_in, &c->v,   &c->vorb,  &c->xorb, &c->work1,
                      &c->work2, &c->scal, &c->hx, &c->hf,    &c->field, &c->dip};
   for (double** b : bufs) {
-    if (*b) hipFree(*b);
+    if (*b) (void)hipFree(*b);
     *b = nullptr;
   }
   double** sbufs[] = {&c->rho_ref, &c->Agsb, &c->Xref, &c->q_ref, &c->v_ref, &c->band_ref,
                       &c->stage};
   for (double** b : sbufs) {
-    if (*b) hipFree(*b);
+    if (*b) (void)hipFree(*b);
     *b = nullptr;
   }
   __bf16** slb[] = {&c->sl_sinv, &c->sl_dh, &c->sl_L2, &c->sl_R2};
   for (__bf16** b : slb) {
-    if (*b) hipFree(*b);
+    if (*b) (void)hipFree(*b);
     *b = nullptr;
   }
   int** eb[] = {&c->e_sinv, &c->e_dh, &c->e_L2, &c->e_R2};
   for (int** b : eb) {
-    if (*b) hipFree(*b);
+    if (*b) (void)hipFree(*b);
     *b = nullptr;
   }
   double** ebufs[] = {&c->sk_s, &c->sk_h, &c->scale_s, &c->scale_h, &c->onsite, &c->mass,
                       &c->GS, &c->GH, &c->W, &c->Dm, &c->Z, &c->dgamma, &c->vel, &c->F,
                       &c->e_kin, &c->e_el};
   for (double** b : ebufs) {
-    if (*b) hipFree(*b);
+    if (*b) (void)hipFree(*b);
     *b = nullptr;
   }
   int** eib[] = {&c->species, &c->norb, &c->atom_of};
   for (int** b : eib) {
-    if (*b) hipFree(*b);
+    if (*b) (void)hipFree(*b);
     *b = nullptr;
   }
-  if (c->orb_off) hipFree(c->orb_off);
+  if (c->orb_off) (void)hipFree(c->orb_off);
   c->orb_off = nullptr;
-  for (hipEvent_t e : c->ev) hipEventDestroy(e);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   c->ev.clear();
-  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   c->stream = nullptr;
 }
 
@@ -368,7 +368,6 @@ void split_init(td_ctx* c) {
 // [delta_re + renorm | -delta_im], X = A_ref rho_ref + [A | B][delta; rho_ref].
 void split_products(td_ctx* c, const double* E, hipEvent_t* ev) {
   const int np = c->np, na = c->na;
-  const size_t m2 = (size_t)np * np;
   hipStream_t st = c->stream;
   HIPCHK(c, td::potential(st, c->gamma, c->dq, c->pos, E, c->orb_off, na, c->v, c->vorb,
                           c->v_ref));
@@ -685,20 +684,20 @@ void step_impl(td_ctx* c, int nsteps, const double* field) {
   if (field) REQUIRE(c, finite_all(field, 3 * (size_t)nsteps), TD_EINVAL, "non-finite field");
   const int na = c->na, np = c->np;
   if (field && c->field_cap < nsteps) {
-    if (c->field) hipFree(c->field);
+    if (c->field) (void)hipFree(c->field);
     c->field = nullptr;
     c->field_cap = 0;
     dalloc(c, &c->field, 3 * (size_t)nsteps);
     c->field_cap = nsteps;
   }
   if (c->dip_cap < nsteps) {
-    if (c->dip) hipFree(c->dip);
+    if (c->dip) (void)hipFree(c->dip);
     c->dip = nullptr;
     c->dip_cap = 0;
     dalloc(c, &c->dip, 3 * (size_t)nsteps);
     if (c->ehr) {
-      if (c->e_kin) hipFree(c->e_kin);
-      if (c->e_el) hipFree(c->e_el);
+      if (c->e_kin) (void)hipFree(c->e_kin);
+      if (c->e_el) (void)hipFree(c->e_el);
       c->e_kin = c->e_el = nullptr;
       dalloc(c, &c->e_kin, (size_t)nsteps);
       dalloc(c, &c->e_el, 3 * (size_t)nsteps);
@@ -828,7 +827,7 @@ void split_gemm_host(td_ctx* c, int ns, int m, int n, int k, const double* A, co
     void* p[4];
     ~Free() {
       for (void* q : p)
-        if (q) hipFree(q);
+        if (q) (void)hipFree(q);
     }
   } guard{{ls, rs, el, fr}};
   td::SliceSrc sa;
@@ -961,7 +960,7 @@ void create_ehr_impl(td_ctx* c, const td_system* s, const td_model* m, const dou
     struct Free {
       td_ctx* p;
       ~Free() {
-        if (p->stream) hipStreamSynchronize(p->stream);
+        if (p->stream) (void)hipStreamSynchronize(p->stream);
         free_all(p);
       }
     } guard{&b};
@@ -1047,7 +1046,7 @@ td_status td_create(const td_system* sys, const td_options* opt, td_ctx** out, c
   td_status st = guarded(c, [&] { create_impl(c, sys, opt); });
   if (st != TD_OK) {
     set_err(err, errlen, c->err);
-    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_all(c);
     delete c;
     return st;
@@ -1225,7 +1224,7 @@ td_status td_create_ehrenfest(const td_system* sys, const td_model* model,
   td_status st = guarded(c, [&] { create_ehr_impl(c, sys, model, velocities, opt); });
   if (st != TD_OK) {
     set_err(err, errlen, c->err);
-    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_all(c);
     delete c;
     return st;
@@ -1288,7 +1287,7 @@ const char* td_status_string(int32_t s) {
 
 void td_destroy(td_ctx* ctx) {
   if (!ctx) return;
-  if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   free_all(ctx);
   delete ctx;
 }
@@ -1327,7 +1326,7 @@ td_status td_util_gemm(int32_t precision, int32_t n_slices, int32_t m, int32_t n
     sync(c);
   });
   set_err(err, errlen, st == TD_OK ? "" : c->err);
-  if (c->stream) hipStreamSynchronize(c->stream);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
   free_all(c);
   return st;
 }
