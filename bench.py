@@ -18,6 +18,8 @@ reported precision, the product (S^-1 H)[Re rho | Im rho] (FP64: 4 n^3
 flop per launch) or its split form (issued bf16 flop per launch), timed
 with HIP events on the library's stream over the timed steps.
 `cpu_baseline` times the CPU oracle on a bounded sample of the workload.
+`probe_batch` (beside the main line, not part of it) times a batch of 64
+probe trajectories with N_orb ~ U[60, 800] against solo contexts.
 """
 from __future__ import annotations
 
@@ -64,6 +66,9 @@ def parse():
     ap.add_argument("--batched", type=int, default=0,
                     help="instead of the N_orb=4096 step: time a batch of this many probe "
                          "trajectories (N_orb ~ U[60, 800]) against solo runs of a sample")
+    ap.add_argument("--batch-summary", type=int, default=64,
+                    help="also time a probe batch of this many trajectories (0 to skip) and "
+                         "report it beside the main line")
     ap.add_argument("--batch-flags", type=int, default=0,
                     help="td_batch_create flags for --batched (1 no graph, 2 / 4 force tiles)")
     ap.add_argument("--validate", type=int, default=0,
@@ -263,56 +268,61 @@ def batched(args):
     the solo figure is the same number of steps of a sample of the members,
     each in its own context, one after the other, scaled to the whole batch.
     """
+    print(json.dumps(batched_measure(args.batched, args.steps, args.warmup, args.batch_flags)),
+          flush=True)
+
+
+def batched_measure(count, steps, warmup, flags=0):
+    """The probe-batch measurement of ``batched`` as a dict."""
     import workloads as W
     from paper_1912_03174_amd import tddftb as T
 
-    count = args.batched
     log(f"generating {count} probe molecules")
     systems, axes = W.probe_batch(count)
     ns = np.array([s.n_orb for s in systems], dtype=np.float64)
     flop_step = float(np.sum(6.0 * ns ** 3))
     t0 = time.perf_counter()
-    b = T.Batch(systems, flags=args.batch_flags)
+    b = T.Batch(systems, flags=flags)
     init_s = time.perf_counter() - t0
     log(f"batch created in {init_s:.1f} s")
     b.kick(np.full(count, 1e-3), axes)
-    if args.warmup:
-        b.step(args.warmup)
+    if warmup:
+        b.step(warmup)
     t0 = time.perf_counter()
-    b.step(args.steps)
+    b.step(steps)
     el = time.perf_counter() - t0
     info = b.info()
     b.close()
-    rate = count * args.steps / el
+    rate = count * steps / el
     # solo contexts on an evenly spaced sample, same steps
     sample = list(range(0, count, max(1, count // 32)))
     solo_s = 0.0
     for m in sample:
         p = T.Propagator(systems[m])
         p.kick(1e-3, axes[m])
-        if args.warmup:
-            p.step(args.warmup)
+        if warmup:
+            p.step(warmup)
         t0 = time.perf_counter()
-        p.step(args.steps)
+        p.step(steps)
         solo_s += time.perf_counter() - t0
         p.close()
-    solo_rate = len(sample) * args.steps / solo_s
+    solo_rate = len(sample) * steps / solo_s
     out = {
         "metric": "probe-trajectory steps/s, batch of N_orb ~ U[60, 800] (FP64)",
-        "value": rate, "unit": "member-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True,
+        "value": rate, "unit": "member-steps/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": 1e3 * el / steps, "higher_is_better": True,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"probe batch x{count}", "members": count,
                    "n_orb_min": int(ns.min()), "n_orb_max": int(ns.max()),
-                   "n_orb_mean": float(ns.mean()), "flags": args.batch_flags},
-        "algorithmic_tflops": flop_step * args.steps / el / 1e12,
-        "fp64_peak_frac": flop_step * args.steps / el / 1e12 / FP64_PEAK_TFLOPS,
+                   "n_orb_mean": float(ns.mean()), "flags": flags},
+        "algorithmic_tflops": flop_step * steps / el / 1e12,
+        "fp64_peak_frac": flop_step * steps / el / 1e12 / FP64_PEAK_TFLOPS,
         "solo_sample": {"members": len(sample), "member_steps_per_s": solo_rate},
         "speedup_vs_solo": rate / solo_rate,
         "init_s": init_s, "tiles": info["bucket_tile"], "bucket_members": info["bucket_members"],
         "tuning_ms": info["bucket_ms"],
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -397,6 +407,12 @@ def main():
         "precisions": {k: {kk: vv for kk, vv in v.items() if kk not in ("dipoles", "charges")}
                        for k, v in res.items()},
     }
+    if args.batch_summary > 0:
+        log(f"probe batch of {args.batch_summary}")
+        bm = batched_measure(args.batch_summary, 50, 5)
+        out["probe_batch"] = {k: bm[k] for k in ("metric", "value", "unit", "ms_per_step",
+                                                 "algorithmic_tflops", "fp64_peak_frac",
+                                                 "speedup_vs_solo", "config", "tiles")}
     if args.cpu_steps > 0:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
