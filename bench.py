@@ -71,6 +71,10 @@ def parse():
                          "report it beside the main line")
     ap.add_argument("--batch-flags", type=int, default=0,
                     help="td_batch_create flags for --batched (1 no graph, 2 / 4 force tiles)")
+    ap.add_argument("--spectrum", type=str, default="",
+                    help="instead of timing: kick the 2944-orbital ribbon, propagate 20000 steps "
+                         "in FP64, compute its absorption spectrum on the GPU and write it to "
+                         "this CSV path")
     ap.add_argument("--validate", type=int, default=0,
                     help="instead of timing: propagate this many steps in FP64 and in "
                          "split-bf16 (--slices) from the same ground state and print the "
@@ -261,6 +265,48 @@ def run(T, w, precision, slices, warmup, steps, field):
     }
 
 
+def spectrum(args):
+    """Kicked 2944-orbital ribbon: dipole series and absorption spectrum."""
+    import workloads as W
+    from paper_1912_03174_amd import tddftb as T
+
+    w = W.spectrum_workload()
+    s = w.system
+    t0 = time.perf_counter()
+    p = T.Propagator(s, dt=w.dt, scc_tol=1e-10)
+    init_s = time.perf_counter() - t0
+    info = p.info()
+    e0, axis = w.kick
+    p.kick(e0, axis)
+    mus = []
+    chunk = 2000
+    t0 = time.perf_counter()
+    for k in range(0, w.n_steps, chunk):
+        mus.append(p.step(min(chunk, w.n_steps - k)))
+        log(f"{k + chunk} steps")
+    el = time.perf_counter() - t0
+    p.close()
+    mu = np.concatenate(mus) @ np.asarray(axis, dtype=np.float64)
+    omega = np.linspace(0.01, 0.6, 2360)
+    tau = 10.0 * W.FS                        # 10 fs damping
+    _, sigma = T.td_spectrum(mu, e0, w.dt, omega, tau=tau)
+    sigma = sigma[0]
+    with open(args.spectrum, "w") as f:
+        f.write("omega_ha,sigma_au\n")
+        for om, sg in zip(omega, sigma):
+            f.write(f"{om:.6f},{sg:.9e}\n")
+    inner = np.nonzero((sigma[1:-1] > sigma[:-2]) & (sigma[1:-1] > sigma[2:]))[0] + 1
+    top = inner[np.argsort(sigma[inner])[::-1][:6]]
+    print(json.dumps({
+        "workload": w.name, "n_orb": s.n_orb, "steps": w.n_steps, "dt_au": w.dt,
+        "steps_per_s": w.n_steps / el, "init_s": init_s,
+        "scc_iterations": info["scc_iterations"], "scc_residual": info["scc_residual"],
+        "damping_fs": 10.0, "peaks": [{"omega_ha": float(omega[i]), "omega_ev": float(omega[i] * 27.211386),
+                                       "sigma_au": float(sigma[i])} for i in sorted(top)],
+        "sigma_min": float(sigma.min()), "sigma_max": float(sigma.max()),
+    }), flush=True)
+
+
 def batched(args):
     """Probe batch: member-steps/s of one batch against solo contexts.
 
@@ -344,6 +390,9 @@ def main():
         return
     if args.batched:
         batched(args)
+        return
+    if args.spectrum:
+        spectrum(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "

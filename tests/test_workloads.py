@@ -68,3 +68,9 @@ def test_sin2_pulse_shape():
     f = w.field(10, 5)
     assert f.shape == (5, 3)
     assert np.allclose(f, W.sin2_pulse(np.arange(10, 15) * 0.2, 0.005, 0.1, 2000.0, (0, 1, 0)))
+
+
+def test_spectrum_strip_counts_and_gap():
+    s = W.strip_c677h236()
+    assert s.n_orb == 2944 and s.species.count("C") == 677 and s.species.count("H") == 236
+    assert s.n_elec % 2 == 0

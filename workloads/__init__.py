@@ -342,6 +342,15 @@ def strip_c640h384(seed=1002) -> System:
     return make_system(sp, pos, seed, name="C640H384 strip")
 
 
+def strip_c677h236(seed=1002) -> System:
+    """7-line armchair strip, 96 columns, 18 pair CH2 sites: N_orb = 2944 as the
+    C640H384 strip, but from the semiconducting ribbon family (non-SCC gap
+    0.038 Ha), so its zero-temperature SCC ground state exists."""
+    pts, bonds = armchair_skeleton(3, 96)
+    sp, pos = molecule(pts, bonds, n_pairs=18, seed=seed)
+    return make_system(sp, pos, seed, name="C677H236 strip")
+
+
 def strip_c938h344(seed=1003) -> System:
     """7-line armchair strip, 133 columns, 2 zigzag + 34 pair CH2 sites: N_orb = 4096."""
     pts, bonds = armchair_skeleton(3, 133)
@@ -470,6 +479,16 @@ def workload(cfg: int) -> Workload:
                                     "0.1 Ha, 0.005 au, in-plane transverse, 10000 steps "
                                     "of 0.2 au")
     raise ValueError(f"unknown workload {cfg}")
+
+
+def spectrum_workload() -> Workload:
+    """Absorption spectrum of a 2944-orbital ribbon: delta kick 0.001 au along
+    the ribbon axis, 20000 steps of 0.2 au (the 2944-orbital workload's
+    protocol on the semiconducting strip_c677h236)."""
+    return Workload("strip2944s", strip_c677h236(), dt=0.2, n_steps=20000,
+                    kick=(1e-3, (1.0, 0.0, 0.0)), laser=None,
+                    description="C677H236 7-line armchair strip, N_orb=2944, delta kick "
+                                "0.001 au along the strip axis, 20000 steps of 0.2 au")
 
 
 # ----------------------------------------------------------------------------
