@@ -75,6 +75,9 @@ def parse():
                     help="instead of timing: kick the 2944-orbital ribbon, propagate 20000 steps "
                          "in FP64, compute its absorption spectrum on the GPU and write it to "
                          "this CSV path")
+    ap.add_argument("--ehrenfest", action="store_true",
+                    help="instead of the clamped-nuclei step: time moving-nuclei steps of the "
+                         "499-atom strip (N_orb=1648) under the sin^2 pump (--steps, --warmup)")
     ap.add_argument("--validate", type=int, default=0,
                     help="instead of timing: propagate this many steps in FP64 and in "
                          "split-bf16 (--slices) from the same ground state and print the "
@@ -307,6 +310,39 @@ def spectrum(args):
     }), flush=True)
 
 
+def ehrenfest(args):
+    """Moving nuclei: steps/s of the pump run on the 499-atom strip."""
+    import workloads as W
+    from paper_1912_03174_amd import tddftb as T
+
+    w = W.ehrenfest_workload()
+    s = w.system
+    m = W.two_centre_model(s)
+    vel = W.thermal_velocities(s, 300.0, seed=5000)
+    t0 = time.perf_counter()
+    e = T.Ehrenfest(s, m, velocities=vel, dt=w.dt, scc_tol=1e-10)
+    init_s = time.perf_counter() - t0
+    field = w.field(0, args.warmup + args.steps)
+    if args.warmup:
+        e.step(args.warmup, field[:args.warmup])
+    t0 = time.perf_counter()
+    e.step(args.steps, field[args.warmup:])
+    el = time.perf_counter() - t0
+    ee, ek = e.energy_series(args.steps)
+    e.close()
+    n = s.n_orb
+    print(json.dumps({
+        "metric": "moving-nuclei steps/s (FP64)", "value": args.steps / el, "unit": "steps/s",
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
+        "config": {"workload": w.name, "n_orb": n, "n_atoms": s.n_atoms,
+                   "field": "sin^2 pump 0.15 Ha, 0.01 au, 10 fs", "nuclei": "300 K"},
+        "trajectory_fs_per_s": args.steps / el * w.dt / W.FS,
+        "product_tflops": 12.0 * n ** 3 * args.steps / el / 1e12,
+        "init_s": init_s, "e_kin_start": float(ek[0]), "e_kin_end": float(ek[-1]),
+        "e_total_change": float((ee[-1] + ek[-1]) - (ee[0] + ek[0])),
+    }), flush=True)
+
+
 def batched(args):
     """Probe batch: member-steps/s of one batch against solo contexts.
 
@@ -393,6 +429,9 @@ def main():
         return
     if args.spectrum:
         spectrum(args)
+        return
+    if args.ehrenfest:
+        ehrenfest(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "

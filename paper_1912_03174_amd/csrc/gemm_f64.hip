@@ -168,15 +168,11 @@ __global__ __launch_bounds__(256) void dgemm_nn(const double* __restrict__ A, in
 // each) for small matrices, where 128-wide tiles would mostly multiply
 // padding. Each output element sees the same MFMA sequence over k in both.
 template <int BT>
+__device__ __forceinline__ void dgemm_tile_body(const GemmProblem* __restrict__ pp, int local);
+
+template <int BT>
 __global__ __launch_bounds__(256) void dgemm_grouped_k(const GemmProblem* __restrict__ probs,
                                                        int nprob, int ntiles) {
-  constexpr int FR = BT / 32;                 // 16 x 16 blocks per wave dimension
-  constexpr int EA = BT * BK / 256;           // A (and B) elements loaded per thread: 8 or 4
-  constexpr int EB = EA;
-  constexpr int LD = BT + PAD;
-  __shared__ double As[2][BK][LD];
-  __shared__ double Bs[2][BK][LD];
-
   // XCD-aware order over the launch's tiles (a problem's tiles stay together).
   const int w = blockIdx.x;
   const int q = ntiles >> 3, r = ntiles & 7;
@@ -187,13 +183,33 @@ __global__ __launch_bounds__(256) void dgemm_grouped_k(const GemmProblem* __rest
     const int mid = (lo + hi + 1) >> 1;
     if (probs[mid].tile0 <= lin) lo = mid; else hi = mid - 1;
   }
-  const GemmProblem* pp = probs + lo;
+  dgemm_tile_body<BT>(probs + lo, lin - probs[lo].tile0);
+}
+
+// One problem passed by value (no device table): the 64-tile form for
+// products with too few 128 x 128 tiles to fill the chip.
+template <int BT>
+__global__ __launch_bounds__(256) void dgemm_single_k(GemmProblem pr) {
+  const int ntiles = pr.tiles_m * pr.tiles_n;
+  const int w = blockIdx.x;
+  const int q = ntiles >> 3, r = ntiles & 7;
+  const int xcd = w & 7, slot = w >> 3;
+  dgemm_tile_body<BT>(&pr, xcd * q + (xcd < r ? xcd : r) + slot);
+}
+
+template <int BT>
+__device__ __forceinline__ void dgemm_tile_body(const GemmProblem* __restrict__ pp, int local) {
+  constexpr int FR = BT / 32;                 // 16 x 16 blocks per wave dimension
+  constexpr int EA = BT * BK / 256;           // A (and B) elements loaded per thread: 8 or 4
+  constexpr int EB = EA;
+  constexpr int LD = BT + PAD;
+  __shared__ double As[2][BK][LD];
+  __shared__ double Bs[2][BK][LD];
   const int tiles_m = pp->tiles_m, tiles_n = pp->tiles_n;
   const int lda = pp->lda, ldb = pp->ldb, ldc = pp->ldc, Kp = pp->K;
   const double* __restrict__ Ap = pp->A;
   const double* __restrict__ Bp = pp->B;
   double* Cp = pp->C;
-  const int local = lin - pp->tile0;
   const int group = GROUP_M * tiles_n;
   const int g = local / group;
   const int first_m = g * GROUP_M;
@@ -317,6 +333,21 @@ hipError_t dgemm(hipStream_t s, int tag, int m, int n, int k, double alpha, cons
   if (lda % 2 || ldb % 2 || lda < k || ldb < n || ldc < n) return hipErrorInvalidValue;
   if (beta != 0.0 && (Cin == nullptr || ldcin < n)) return hipErrorInvalidValue;
   const int tm = m / BM, tn = n / BN;
+  if (tm * tn < 512 && alpha == 1.0 && beta == 0.0) {
+    // too few 128-wide tiles for 256 CUs: 64-wide tiles, same sums in the same order
+    GemmProblem pr{};
+    pr.A = A;
+    pr.B = B;
+    pr.C = C;
+    pr.lda = lda;
+    pr.ldb = ldb;
+    pr.ldc = ldc;
+    pr.K = k;
+    pr.tiles_m = m / 64;
+    pr.tiles_n = n / 64;
+    hipLaunchKernelGGL(dgemm_single_k<64>, dim3(pr.tiles_m * pr.tiles_n), dim3(256), 0, s, pr);
+    return hipGetLastError();
+  }
   const dim3 grid(tm * tn), block(256);
   switch (tag) {
     case 1:

@@ -481,6 +481,18 @@ def workload(cfg: int) -> Workload:
     raise ValueError(f"unknown workload {cfg}")
 
 
+def ehrenfest_workload() -> Workload:
+    """Moving-nuclei pump run: 499-atom 7-line armchair strip (C383H116,
+    N_orb = 1648), nuclei at 300 K (thermal_velocities seed 5000), sin^2 pump
+    0.15 Ha, 0.01 au, t_p = 10 fs along the strip, 5000 steps of 0.2 au."""
+    s = small_strip(54, 0, seed=1005, width=3)
+    t_p = 10.0 * FS
+    return Workload("strip1648md", s, dt=0.2, n_steps=5000, kick=None,
+                    laser=dict(e0=0.01, omega=0.15, t_p=t_p, direction=(1.0, 0.0, 0.0)),
+                    description="C383H116 strip, N_orb=1648, moving nuclei at 300 K, sin^2 "
+                                "pump 0.15 Ha, 0.01 au, 10 fs, 5000 steps of 0.2 au")
+
+
 def spectrum_workload() -> Workload:
     """Absorption spectrum of a 2944-orbital ribbon: delta kick 0.001 au along
     the ribbon axis, 20000 steps of 0.2 au (the 2944-orbital workload's
