@@ -161,26 +161,35 @@ __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
 
   const int nt = p.tiles_m * p.tiles_n;
   const int w = blockIdx.x;
-  const int q = nt >> 3, r = nt & 7;
-  const int xcd = w & 7, slot = w >> 3;
-  const int lin = xcd * q + (xcd < r ? xcd : r) + slot;
-  const int group = GROUP_M * p.tiles_n;
-  const int g = lin / group;
+  const int xcd = w & 7, slot = w >> 3;                    // workgroups go to XCDs round-robin
+  // Column tiles below n_split use K = k_hi, the others K = k_lo. When these
+  // are two equal halves with a tile count per half divisible by 8, every
+  // XCD takes the same share of each half, the long-K tiles first: its CUs
+  // then finish together, with no long tile left over at the end.
+  const int half = p.tiles_n / 2;
+  const int per_half = p.tiles_m * half;
+  const bool halves = p.k_lo != p.k_hi && 2 * p.n_split == p.tiles_n * BN && per_half % 8 == 0;
+  int idx, cols, col0;
+  if (halves) {
+    const int share = per_half >> 3;
+    const bool second = slot >= share;
+    idx = xcd * share + (second ? slot - share : slot);
+    cols = half;
+    col0 = second ? half : 0;
+  } else {
+    const int q = nt >> 3, r = nt & 7;
+    idx = xcd * q + (xcd < r ? xcd : r) + slot;          // contiguous range per XCD
+    cols = p.tiles_n;
+    col0 = 0;
+  }
+  // GROUP_M row tiles side by side share every column tile's K panel in L2
+  const int group = GROUP_M * cols;
+  const int g = idx / group;
   const int first_m = g * GROUP_M;
   const int gsz = (p.tiles_m - first_m) < GROUP_M ? (p.tiles_m - first_m) : GROUP_M;
-  const int in_g = lin - g * group;
+  const int in_g = idx - g * group;
   const int m0 = (first_m + in_g % gsz) * BM;
-  // When the columns below n_split (K = k_hi) and above it (K = k_lo) are
-  // two equal halves, runs of `run` column tiles alternate between the
-  // halves, so every XCD's contiguous range of tiles holds as much long-K as
-  // short-K work while neighbouring tiles still share K positions (L2 reuse).
-  const int ci = in_g / gsz;
-  const int half = p.tiles_n / 2;
-  const bool alternate = p.k_lo != p.k_hi && 2 * p.n_split == p.tiles_n * BN;
-  int run = 16;
-  while (run > 1 && half % run) run >>= 1;
-  const int chunk = ci / run;
-  const int n0 = (alternate ? ((chunk & 1) * half + (chunk >> 1) * run + ci % run) : ci) * BN;
+  const int n0 = (col0 + in_g / gsz) * BN;
   const int K = (n0 < p.n_split) ? p.k_hi : p.k_lo;
   const int nk = K / BK;
 
