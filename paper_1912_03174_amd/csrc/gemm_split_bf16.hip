@@ -439,16 +439,25 @@ hipError_t launch_split(hipStream_t st, const SplitGemm& g) {
 
 // Same slicing for rows of at most 128 CPL values, two waves per row: each
 // lane keeps its CPL values in registers between the row maximum and the
-// slicing, so the source is read from memory once instead of twice.
+// slicing, so the source is read from memory once instead of twice. A lane
+// holds CPL / 8 runs of 8 consecutive columns, read as 16-byte pairs, and
+// writes each slice of a run as one 16-byte store (half a k block).
 // SLICE_SUM_AND_M1 slices two rows (M0 + M1 and M1) from one read of M1.
 template <int S>
-__device__ __forceinline__ void slice_store(double x, int e, __bf16* o) {
-  double rr = ldexp(x, 8 - e);
+__device__ __forceinline__ void slice_store8(const double* x, int e, __bf16* o) {
+  double rr[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) rr[i] = ldexp(x[i], 8 - e);
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const double sig = rint(rr);
-    o[s * 16] = (__bf16)(float)ldexp(sig, -8 * s);
-    rr = (rr - sig) * 256.0;
+    bf16x8 v;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const double sig = rint(rr[i]);
+      v[i] = (__bf16)(float)ldexp(sig, -8 * s);
+      rr[i] = (rr[i] - sig) * 256.0;
+    }
+    *reinterpret_cast<bf16x8*>(o + s * 16) = v;
   }
 }
 
@@ -460,9 +469,22 @@ __device__ __forceinline__ double pair_max(double m, double* wmax) {
   return fmax(wmax[(threadIdx.x >> 7) * 2], wmax[(threadIdx.x >> 7) * 2 + 1]);
 }
 
+// 8 consecutive doubles from a 16-byte aligned address
+__device__ __forceinline__ void load8(const double* p, double* v) {
+  const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double2 t = q[i];
+    v[2 * i] = t.x;
+    v[2 * i + 1] = t.y;
+  }
+}
+
 template <int S, int MODE, int CPL>
 __global__ __launch_bounds__(256) void k_slice_rows_cached(SliceSrc src, int rows, int cols,
                                                            __bf16* out, int ldo, int* exps) {
+  static_assert(CPL % 8 == 0, "runs of 8 columns");
+  constexpr int RUNS = CPL / 8;
   __shared__ double wmax[4], wmax2[4];
   const int row = blockIdx.x * 2 + (threadIdx.x >> 7);
   const int l = threadIdx.x & 127;
@@ -471,28 +493,37 @@ __global__ __launch_bounds__(256) void k_slice_rows_cached(SliceSrc src, int row
   double x[CPL], y[TWO ? CPL : 1];
   double m = 0.0, m2 = 0.0;
 #pragma unroll
-  for (int j = 0; j < CPL; ++j) {
-    const int c = l + 128 * j;
-    double val = 0.0, val2 = 0.0;
+  for (int g = 0; g < RUNS; ++g) {
+    const int c = 8 * (l + 128 * g);          // cols is a multiple of 16: runs are whole
+    double* xv = x + 8 * g;
+    double a[8], b[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = b[i] = 0.0;
     if (live && c < cols) {
-      if (MODE == SLICE_PLAIN) {
-        val = src.sign * src.M0[(size_t)row * src.ld0 + c];
-      } else if (MODE == SLICE_SUM) {
-        val = src.M0[(size_t)row * src.ld0 + c] + src.M1[(size_t)row * src.ld1 + c];
-      } else if (MODE == SLICE_SUM_AND_M1) {
-        val2 = src.M1[(size_t)row * src.ld1 + c];
-        val = src.M0[(size_t)row * src.ld0 + c] + val2;
-      } else if (MODE == SLICE_RENORM) {
-        val = src.M0[(size_t)row * src.ld0 + c] - src.cs[0] * src.M1[(size_t)row * src.ld1 + c];
-      } else {
-        val = 0.5 * src.M0[(size_t)row * src.ld0 + c] * (src.v[row] + src.v[c]);
-      }
+      load8(src.M0 + (size_t)row * src.ld0 + c, a);
+      if (MODE == SLICE_SUM || MODE == SLICE_SUM_AND_M1 || MODE == SLICE_RENORM)
+        load8(src.M1 + (size_t)row * src.ld1 + c, b);
+      else if (MODE == SLICE_DH)
+        load8(src.v + c, b);
     }
-    x[j] = val;
-    m = fmax(m, fabs(val));
-    if constexpr (TWO) {
-      y[j] = val2;
-      m2 = fmax(m2, fabs(val2));
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      double val;
+      if (MODE == SLICE_PLAIN) {
+        val = src.sign * a[i];
+      } else if (MODE == SLICE_SUM || MODE == SLICE_SUM_AND_M1) {
+        val = a[i] + b[i];
+      } else if (MODE == SLICE_RENORM) {
+        val = a[i] - src.cs[0] * b[i];
+      } else {
+        val = 0.5 * a[i] * (src.v[row < rows ? row : 0] + b[i]);
+      }
+      xv[i] = val;
+      m = fmax(m, fabs(val));
+      if constexpr (TWO) {
+        y[8 * g + i] = b[i];
+        m2 = fmax(m2, fabs(b[i]));
+      }
     }
   }
   m = pair_max(m, wmax);
@@ -506,13 +537,17 @@ __global__ __launch_bounds__(256) void k_slice_rows_cached(SliceSrc src, int row
     if (TWO) src.exps2[row] = e2;
   }
 #pragma unroll
-  for (int j = 0; j < CPL; ++j) {
-    const int c = l + 128 * j;
+  for (int g = 0; g < RUNS; ++g) {
+    const int c = 8 * (l + 128 * g);
     if (c < cols) {
-      if (MODE == SLICE_RENORM) src.M0w[(size_t)row * src.ld0 + c] = x[j];
+      if (MODE == SLICE_RENORM) {
+        double2* w = reinterpret_cast<double2*>(src.M0w + (size_t)row * src.ld0 + c);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = make_double2(x[8 * g + 2 * i], x[8 * g + 2 * i + 1]);
+      }
       const size_t at = (size_t)row * ldo + (size_t)(c >> 4) * (16 * S) + (c & 15);
-      slice_store<S>(x[j], e, out + at);
-      if constexpr (TWO) slice_store<S>(y[j], e2, src.out2 + at);
+      slice_store8<S>(x + 8 * g, e, out + at);
+      if constexpr (TWO) slice_store8<S>(y + 8 * g, e2, src.out2 + at);
     }
   }
 }

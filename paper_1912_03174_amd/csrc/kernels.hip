@@ -114,10 +114,13 @@ constexpr int TLD = TS + 1;
 enum { PAIR_LEAPFROG = 0, PAIR_HERM = 1, PAIR_SYM = 2 };
 
 // Block (bx, by) with by <= bx handles tiles (by, bx) and (bx, by).
-// Thread t: row t/8 of the tile, 4 consecutive columns at 4*(t%8).
+// Thread t: row t/8 of the tile, 4 consecutive columns at 4*(t%8), moved as
+// two 16-byte pairs. Every global read of a thread (both tiles, and the
+// addend b of the leapfrog) is issued before its first write: the output
+// may alias b or x (in-place update), and reads then stores in program order
+// keep the loads in flight together instead of one round trip per store.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_pair(const double* __restrict__ xre,
-                                              const double* __restrict__ xim, int ldx,
+__global__ __launch_bounds__(256) void k_pair(const double* xre, const double* xim, int ldx,
                                               const double* bre, const double* bim, int ldb,
                                               double* ore, double* oim, int ldo, double f) {
   const int bi = blockIdx.y, bj = blockIdx.x;
@@ -128,38 +131,75 @@ __global__ __launch_bounds__(256) void k_pair(const double* __restrict__ xre,
   const int tr = t >> 3, tc = (t & 7) * 4;
   const bool diag = (bi == bj);
   const int nt = diag ? 1 : 2;
-  for (int p = 0; p < nt; ++p) {
-    const int ti = p ? bj : bi, tj = p ? bi : bj;
-    const size_t g = (size_t)(ti * TS + tr) * ldx + tj * TS + tc;
+  double2 xr[2][2], xi[2][2], br[2][2], bm[2][2];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      sre[p][tr][tc + c] = xre[g + c];
-      if (MODE != PAIR_SYM) sim[p][tr][tc + c] = xim[g + c];
+  for (int p = 0; p < 2; ++p) {
+    if (p < nt) {
+      const int ti = p ? bj : bi, tj = p ? bi : bj;
+      const size_t g = (size_t)(ti * TS + tr) * ldx + tj * TS + tc;
+      xr[p][0] = *reinterpret_cast<const double2*>(xre + g);
+      xr[p][1] = *reinterpret_cast<const double2*>(xre + g + 2);
+      if (MODE != PAIR_SYM) {
+        xi[p][0] = *reinterpret_cast<const double2*>(xim + g);
+        xi[p][1] = *reinterpret_cast<const double2*>(xim + g + 2);
+      }
+      if (MODE == PAIR_LEAPFROG) {
+        const size_t gb = (size_t)(ti * TS + tr) * ldb + tj * TS + tc;
+        br[p][0] = *reinterpret_cast<const double2*>(bre + gb);
+        br[p][1] = *reinterpret_cast<const double2*>(bre + gb + 2);
+        bm[p][0] = *reinterpret_cast<const double2*>(bim + gb);
+        bm[p][1] = *reinterpret_cast<const double2*>(bim + gb + 2);
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    if (p < nt) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        sre[p][tr][tc + 2 * h] = xr[p][h].x;
+        sre[p][tr][tc + 2 * h + 1] = xr[p][h].y;
+        if (MODE != PAIR_SYM) {
+          sim[p][tr][tc + 2 * h] = xi[p][h].x;
+          sim[p][tr][tc + 2 * h + 1] = xi[p][h].y;
+        }
+      }
     }
   }
   __syncthreads();
-  for (int p = 0; p < nt; ++p) {
-    const int ti = p ? bj : bi, tj = p ? bi : bj;
-    const int q = diag ? 0 : (p ^ 1);   // tile holding the transpose partner
-    const size_t go = (size_t)(ti * TS + tr) * ldo + tj * TS + tc;
-    const size_t gb = (size_t)(ti * TS + tr) * ldb + tj * TS + tc;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int cc = tc + c;
-      const double are = sre[p][tr][cc], aret = sre[q][cc][tr];
-      if (MODE == PAIR_LEAPFROG) {
-        const double aim = sim[p][tr][cc], aimt = sim[q][cc][tr];
-        const double dre = aim + aimt;     // Re rhodot = Xim + Xim^T
-        const double dim = aret - are;     // Im rhodot = Xre^T - Xre
-        ore[go + c] = bre[gb + c] + f * dre;
-        oim[go + c] = bim[gb + c] + f * dim;
-      } else if (MODE == PAIR_HERM) {
-        const double aim = sim[p][tr][cc], aimt = sim[q][cc][tr];
-        ore[go + c] = 0.5 * (are + aret);
-        oim[go + c] = 0.5 * (aim - aimt);
-      } else {
-        ore[go + c] = 0.5 * (are + aret);
-        if (oim) oim[go + c] = 0.0;
+  for (int p = 0; p < 2; ++p) {
+    if (p < nt) {
+      const int ti = p ? bj : bi, tj = p ? bi : bj;
+      const int q = diag ? 0 : (p ^ 1);   // tile holding the transpose partner
+      const size_t go = (size_t)(ti * TS + tr) * ldo + tj * TS + tc;
+      double r[4], m[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int cc = tc + c;
+        const double are = sre[p][tr][cc], aret = sre[q][cc][tr];
+        if (MODE == PAIR_LEAPFROG) {
+          const double aim = sim[p][tr][cc], aimt = sim[q][cc][tr];
+          const double dre = aim + aimt;     // Re rhodot = Xim + Xim^T
+          const double dim = aret - are;     // Im rhodot = Xre^T - Xre
+          const double b_re = (c & 1) ? br[p][c >> 1].y : br[p][c >> 1].x;
+          const double b_im = (c & 1) ? bm[p][c >> 1].y : bm[p][c >> 1].x;
+          r[c] = b_re + f * dre;
+          m[c] = b_im + f * dim;
+        } else if (MODE == PAIR_HERM) {
+          const double aim = sim[p][tr][cc], aimt = sim[q][cc][tr];
+          r[c] = 0.5 * (are + aret);
+          m[c] = 0.5 * (aim - aimt);
+        } else {
+          r[c] = 0.5 * (are + aret);
+          m[c] = 0.0;
+        }
+      }
+      *reinterpret_cast<double2*>(ore + go) = make_double2(r[0], r[1]);
+      *reinterpret_cast<double2*>(ore + go + 2) = make_double2(r[2], r[3]);
+      if (MODE != PAIR_SYM || oim) {
+        *reinterpret_cast<double2*>(oim + go) = make_double2(m[0], m[1]);
+        *reinterpret_cast<double2*>(oim + go + 2) = make_double2(m[2], m[3]);
       }
     }
   }
