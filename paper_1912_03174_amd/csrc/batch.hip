@@ -368,7 +368,10 @@ void create_impl(td_batch* b, int n, const td_system* systems, const td_options*
 
 void step_impl(td_batch* b, int n, const double* field) {
   REQUIRE(b, n >= 0, TD_EINVAL, "n must be >= 0");
-  if (n == 0) return;
+  if (n == 0) {
+    b->last_n = 0;     // an empty call records no dipoles
+    return;
+  }
   if (field) {
     for (size_t i = 0; i < 3 * (size_t)n; ++i)
       REQUIRE(b, std::isfinite(field[i]), TD_EINVAL, "non-finite field");

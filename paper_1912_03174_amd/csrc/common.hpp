@@ -184,6 +184,8 @@ hipError_t kick_phase(hipStream_t s, double* re, double* im, int ld, const doubl
 hipError_t scaled_identity(hipStream_t s, double* X, int np, int n, double c);
 // T = 2 I_n - T (np x np).
 hipError_t two_minus(hipStream_t s, double* T, int np, int n);
+// y = 2 x - y over len elements
+hipError_t extrapolate(hipStream_t s, const double* x, double* y, size_t len);
 // X = (emax I_n - T) / (emax - emin).
 hipError_t sp2_init(hipStream_t s, const double* T, double* X, int np, int n, double emax,
                     double emin);

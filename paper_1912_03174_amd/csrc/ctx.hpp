@@ -60,6 +60,8 @@ struct td_ctx {
   double *onsite = nullptr, *mass = nullptr;
   double *GS = nullptr, *GH = nullptr;   // 3 np x np each
   double *W = nullptr, *Dm = nullptr;    // np x np
+  double *Sinv_prev = nullptr;           // np x np: S^-1 of the previous positions
+  bool sinv_prev_ok = false;
   double *Z = nullptr;                   // np x 2np
   double *dgamma = nullptr;              // na x na x 3
   double *vel = nullptr, *F = nullptr;   // na x 3

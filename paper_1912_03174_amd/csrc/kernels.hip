@@ -226,6 +226,12 @@ __global__ void k_scaled_identity(double* X, int np, int n, double c) {
   X[idx] = (r == cc && r < n) ? c : 0.0;
 }
 
+// y <- 2 x - y
+__global__ void k_extrapolate(const double* __restrict__ x, double* __restrict__ y, size_t len) {
+  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx < len) y[idx] = 2.0 * x[idx] - y[idx];
+}
+
 __global__ void k_two_minus(double* T, int np, int n) {
   const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= (size_t)np * np) return;
@@ -632,6 +638,12 @@ hipError_t kick_phase(hipStream_t s, double* re, double* im, int ld, const doubl
 hipError_t scaled_identity(hipStream_t s, double* X, int np, int n, double c) {
   hipLaunchKernelGGL(k_scaled_identity, dim3(blocks_for((size_t)np * np)), dim3(256), 0, s, X,
                      np, n, c);
+  return hipGetLastError();
+}
+
+hipError_t extrapolate(hipStream_t s, const double* x, double* y, size_t len) {
+  if (len == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_extrapolate, dim3(blocks_for(len)), dim3(256), 0, s, x, y, len);
   return hipGetLastError();
 }
 

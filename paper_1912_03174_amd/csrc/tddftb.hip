@@ -67,7 +67,8 @@ void free_all(td_ctx* c) {
     *b = nullptr;
   }
   double** ebufs[] = {&c->sk_s, &c->sk_h, &c->scale_s, &c->scale_h, &c->onsite, &c->mass,
-                      &c->GS, &c->GH, &c->W, &c->Dm, &c->Z, &c->dgamma, &c->vel, &c->F,
+                      &c->GS, &c->GH, &c->W, &c->Dm, &c->Sinv_prev, &c->Z, &c->dgamma,
+                      &c->vel, &c->F,
                       &c->e_kin, &c->e_el};
   for (double** b : ebufs) {
     if (*b) (void)hipFree(*b);
@@ -129,9 +130,22 @@ void refresh(td_ctx* c) {
 // S^-1 by the Newton-Schulz iteration X <- X (2 - S X), X_0 = I / g with g
 // a Gershgorin bound of the largest eigenvalue of S.
 // With `warm`, the iteration starts from the current S^-1 (the inverse of a
-// nearby S, as after a nuclear step).
+// nearby S, as after a nuclear step); when the inverse at the positions
+// before is kept too (moving nuclei), from the linear extrapolation
+// 2 X_n - X_{n-1} along the trajectory, whose residual is second order in
+// the step instead of first.
 void inverse_overlap(td_ctx* c, bool warm = false) {
   const int n = c->n, np = c->np;
+  if (warm && c->Sinv_prev) {
+    if (c->sinv_prev_ok) {
+      HIPCHK(c, td::extrapolate(c->stream, c->Sinv, c->Sinv_prev, (size_t)np * np));
+      std::swap(c->Sinv, c->Sinv_prev);     // Sinv = 2 X_n - X_{n-1}, Sinv_prev = X_n
+    } else {
+      HIPCHK(c, hipMemcpyAsync(c->Sinv_prev, c->Sinv, sizeof(double) * np * (size_t)np,
+                               hipMemcpyDeviceToDevice, c->stream));
+    }
+    c->sinv_prev_ok = true;
+  }
   if (!warm) {
     HIPCHK(c, td::gershgorin(c->stream, c->S, np, n, c->work1, c->work2, c->scal + SC_BOUNDS));
     double b[2];
@@ -683,7 +697,10 @@ void ehr_step(td_ctx* c, int k, const double* E) {
 
 void step_impl(td_ctx* c, int nsteps, const double* field) {
   REQUIRE(c, nsteps >= 0, TD_EINVAL, "n must be >= 0");
-  if (nsteps == 0) return;
+  if (nsteps == 0) {
+    c->last_n = 0;     // an empty call records no dipoles (or energies)
+    return;
+  }
   if (field) REQUIRE(c, finite_all(field, 3 * (size_t)nsteps), TD_EINVAL, "non-finite field");
   const int na = c->na, np = c->np;
   if (field && c->field_cap < nsteps) {
@@ -1004,6 +1021,8 @@ void create_ehr_impl(td_ctx* c, const td_system* s, const td_model* m, const dou
   const size_t m2 = (size_t)c->np * c->np;
   dalloc(c, &c->W, m2);
   dalloc(c, &c->Dm, m2);
+  dalloc(c, &c->Sinv_prev, m2);
+  c->sinv_prev_ok = false;
   dalloc(c, &c->Z, 2 * m2);
   c->ehr = true;
   c->vel_half = false;
