@@ -507,6 +507,24 @@ def spectrum_workload() -> Workload:
 # seeded random matrices (no physics)
 # ----------------------------------------------------------------------------
 
+def atomic_shells(system: System, u_by_shell=None):
+    """Shells of the synthetic basis for the on-site corrections: one s
+    shell per atom and one p shell per carbon, as contiguous orbital ranges.
+    Returns (shell_offset [n_shells + 1] int32, shell_u [n_shells]) with
+    shell_u taken from ``u_by_shell`` keyed by (species, 's' | 'p')
+    (missing keys: 0)."""
+    u_by_shell = u_by_shell or {}
+    off, us = [0], []
+    for a, sp in enumerate(system.species):
+        lo, hi = int(system.orb_offset[a]), int(system.orb_offset[a + 1])
+        off.append(lo + 1)
+        us.append(float(u_by_shell.get((sp, "s"), 0.0)))
+        if hi - lo == 4:
+            off.append(hi)
+            us.append(float(u_by_shell.get((sp, "p"), 0.0)))
+    return np.array(off, dtype=np.int32), np.array(us)
+
+
 def random_hermitian_pair(n, seed, scale=1e-3, base=None):
     """Seeded (Re, Im) of a Hermitian matrix: symmetric Re, antisymmetric Im."""
     rng = np.random.default_rng(seed)
