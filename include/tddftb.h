@@ -73,6 +73,22 @@ typedef enum {
  * order, and keeps no reference. Without the flag they are host pointers. */
 #define TD_DEVICE_PTRS 1u
 
+/* td_system.plus_u: the on-site corrections of Sec. 3.2 added to the SCC
+ * Hamiltonian in the ground state and at every step: the fully-localised
+ * limit of DFTB+U (Eqs. 21-23) or pseudo-SIC (Eqs. 24-25). Per shell b
+ * (a contiguous range of orbitals of one atom) with U_b = shell_u[b], the
+ * dual block population n_b = 1/2 (Re(rho) S + S Re(rho)) restricted to the
+ * shell (Eq. 23; the density is spin-summed, n_b / 2 per spin), the energy
+ *   FLL:  dE = sum_b -(U_b / 4) sum_uv n_uv^2 + (U_b / 2) sum_u n_uu
+ *   pSIC: dE = sum_b -(U_b / 4) sum_uv n_uv^2
+ * and its derivative V_b = -(U_b / 2) (n_b - 1) (FLL) or -(U_b / 2) n_b
+ * (pSIC) enters H as 1/2 (S V + V S), V block diagonal. FP64 contexts
+ * only: TD_SPLIT_BF16, batches and moving nuclei return TD_ENOTSUP. */
+#define TD_PLUS_U_NONE 0
+#define TD_PLUS_U_FLL 1
+#define TD_PLUS_U_PSIC 2
+#define TD_PLUS_U_MAX_SHELL 7   /* orbitals per shell (up to an f shell) */
+
 /* The model: positions, overlap S, non-SCC Hamiltonian H0 (Sec. 2.1,
  * Eq. 6), charge kernel gamma (Sec. 2.1, Eq. 3), reference populations
  * q0, and the occupations of the ground state (Sec. 2.1): either occ,
@@ -97,6 +113,13 @@ typedef struct {
   const double *rho0;          /* optional, see above                           */
   const double *occ;           /* optional [n_orb], see above                   */
   uint32_t flags;              /* 0 or TD_DEVICE_PTRS                           */
+  int32_t plus_u;              /* TD_PLUS_U_NONE / _FLL / _PSIC (see above)     */
+  int32_t n_shells;            /* shells when plus_u != TD_PLUS_U_NONE          */
+  const int32_t *shell_offset; /* [n_shells + 1]: shell b is orbitals           */
+                               /* [shell_offset[b], shell_offset[b + 1]), 1 to  */
+                               /* TD_PLUS_U_MAX_SHELL orbitals of one atom;     */
+                               /* shell_offset[0] = 0, last = n_orb             */
+  const double *shell_u;       /* [n_shells] U_eff, hartree, finite and >= 0    */
 } td_system;
 
 typedef struct {
@@ -145,9 +168,11 @@ TD_API void td_default_options(td_options *opt);
 
 /* Creates a context (Sec. 2.3): copies the model to the GPU, forms S^-1,
  * and either takes rho0 or solves the SCC ground state (Sec. 2.1) by
- * density-matrix purification. The ground state is the initial density
- * with no leapfrog history. On failure *out is NULL and err (if not NULL)
- * receives a message of at most errlen bytes. */
+ * density-matrix purification (with plus_u, charges and block populations
+ * are made self-consistent together). The ground state is the initial
+ * density with no leapfrog history. Invalid shells return TD_EINVAL. On
+ * failure *out is NULL and err (if not NULL) receives a message of at
+ * most errlen bytes. */
 TD_API td_status td_create(const td_system *sys, const td_options *opt, td_ctx **out,
                            char *err, int32_t errlen);
 
@@ -254,8 +279,8 @@ typedef struct {
 /* Creates a context with moving nuclei. sys gives positions, orb_offset,
  * q0, the occupations and optionally rho0 as for td_create; its S, H0 and
  * gamma are ignored (built from the model, on the GPU). velocities
- * [n_atoms * 3] bohr per au of time (NULL: at rest). FP64 precision only
- * (TD_ENOTSUP otherwise). td_step then advances electrons and nuclei with
+ * [n_atoms * 3] bohr per au of time (NULL: at rest). FP64 precision and
+ * no plus_u (TD_ENOTSUP otherwise). td_step then advances electrons and nuclei with
  * the same dt; td_kick, td_get_rho / td_set_rho act on the electrons and
  * keep the nuclei. */
 TD_API td_status td_create_ehrenfest(const td_system *sys, const td_model *model,
@@ -304,7 +329,7 @@ typedef struct {
 /* Creates a batch of n >= 1 trajectories, systems[m] as for td_create
  * (host or device pointers per its flags; rho0 NULL: SCC ground state).
  * opt applies to every member and must ask for TD_FP64 (split-bf16
- * batches return TD_ENOTSUP). flags: TD_BATCH_* bits. Without a TILE flag
+ * batches, and members with plus_u, return TD_ENOTSUP). flags: TD_BATCH_* bits. Without a TILE flag
  * the library times both product tiles on each size bucket's members and
  * keeps the faster one. The batch owns one stream (opt.hip_stream, or its
  * own); a failure names the member in err. */

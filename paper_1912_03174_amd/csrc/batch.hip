@@ -289,6 +289,9 @@ void create_impl(td_batch* b, int n, const td_system* systems, const td_options*
           "TD_BATCH_TILE_128 and TD_BATCH_TILE_64 exclude each other");
   REQUIRE(b, opt->precision == TD_FP64, TD_ENOTSUP, "batches run in TD_FP64 precision only");
   REQUIRE(b, opt->dt > 0 && std::isfinite(opt->dt), TD_EINVAL, "dt must be positive");
+  for (int m = 0; m < n; ++m)
+    REQUIRE(b, systems[m].plus_u == TD_PLUS_U_NONE, TD_ENOTSUP,
+            "member " + std::to_string(m) + ": batches have no on-site corrections (plus_u)");
   b->nm = n;
   b->opt = *opt;
   b->flags = flags;

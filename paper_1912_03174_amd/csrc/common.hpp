@@ -15,6 +15,7 @@ namespace td {
 // to a multiple of kPad with zeros.
 constexpr int kGemmTile = 128;
 constexpr int kPad = 128;
+constexpr int kPlusUMaxShell = 7;   // orbitals per shell of the on-site corrections
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -184,6 +185,19 @@ hipError_t kick_phase(hipStream_t s, double* re, double* im, int ld, const doubl
 hipError_t scaled_identity(hipStream_t s, double* X, int np, int n, double c);
 // T = 2 I_n - T (np x np).
 hipError_t two_minus(hipStream_t s, double* T, int np, int n);
+
+// On-site corrections (plus_u_kernels.hip). Shell blocks are stored as
+// kPlusUMaxShell^2 doubles per shell (row-major, zero beyond the shell).
+// n_out: block populations of Re(rho) (rho wide, leading dimension ldr);
+// e_sh (optional): each shell's correction energy. mode: 1 FLL, 2 pSIC.
+hipError_t block_populations(hipStream_t s, const double* rho, int ldr, const double* S, int lds,
+                             const int* sh_off, const double* sh_u, int nsh, int max_shell,
+                             int mode, int ncols, double* n_out, double* e_sh);
+hipError_t plus_u_potential(hipStream_t s, const double* n, const int* sh_off, const double* sh_u,
+                            int nsh, int mode, double* V);
+hipError_t assemble_h_plus_u(hipStream_t s, const double* H0, const double* S, const double* vorb,
+                             const int* sh_of, const int* sh_off, const double* V, double* H,
+                             int np);
 // y = 2 x - y over len elements
 hipError_t extrapolate(hipStream_t s, const double* x, double* y, size_t len);
 // X = (emax I_n - T) / (emax - emin).

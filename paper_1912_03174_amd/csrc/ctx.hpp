@@ -25,6 +25,12 @@ struct td_ctx {
   double *q_orb = nullptr, *dq = nullptr, *dq_in = nullptr, *v = nullptr, *vorb = nullptr;
   double *xorb = nullptr, *work1 = nullptr, *work2 = nullptr, *scal = nullptr;
   double *hx = nullptr, *hf = nullptr;
+  // on-site corrections (Sec. 3.2): shells, their U, block populations n,
+  // potentials V and energies; the SCC mixing vector [dq | n blocks]
+  int plus_u = 0, nsh = 0, max_shell = 0, mix_len = 0;
+  int *sh_off = nullptr, *sh_of = nullptr;
+  double *sh_u = nullptr, *sh_n = nullptr, *sh_v = nullptr, *sh_e = nullptr;
+  double *mix_in = nullptr, *mix_out = nullptr, *mix_hx = nullptr, *mix_hf = nullptr;
   double* field = nullptr;
   int field_cap = 0;
   double* dip = nullptr;

@@ -69,12 +69,13 @@ void free_all(td_ctx* c) {
   double** ebufs[] = {&c->sk_s, &c->sk_h, &c->scale_s, &c->scale_h, &c->onsite, &c->mass,
                       &c->GS, &c->GH, &c->W, &c->Dm, &c->Sinv_prev, &c->Z, &c->dgamma,
                       &c->vel, &c->F,
-                      &c->e_kin, &c->e_el};
+                      &c->e_kin, &c->e_el, &c->sh_u, &c->sh_n, &c->sh_v, &c->sh_e,
+                      &c->mix_in, &c->mix_out, &c->mix_hx, &c->mix_hf};
   for (double** b : ebufs) {
     if (*b) (void)hipFree(*b);
     *b = nullptr;
   }
-  int** eib[] = {&c->species, &c->norb, &c->atom_of};
+  int** eib[] = {&c->species, &c->norb, &c->atom_of, &c->sh_off, &c->sh_of};
   for (int** b : eib) {
     if (*b) (void)hipFree(*b);
     *b = nullptr;
@@ -219,20 +220,37 @@ void purify(td_ctx* c) {
   HIPCHK(c, td::pair_sym(c->stream, X2, np, c->rho_cur, c->rho_cur + np, 2 * np, np));
 }
 
+void assemble_hamiltonian(td_ctx* c, const double* n_blocks);
+void block_pops(td_ctx* c, double* out);
+
+// With on-site corrections the mixed vector is [dq | block populations]:
+// H is built from the mixed charges and populations, and both are
+// compared with those of the purified density.
 void ground_state(td_ctx* c) {
-  const int na = c->na, np = c->np;
+  const int na = c->na;
   const int m = std::max(1, std::min(8, c->opt.mix_history));
-  HIPCHK(c, hipMemsetAsync(c->dq_in, 0, sizeof(double) * na, c->stream));
+  const bool pu = c->plus_u != TD_PLUS_U_NONE;
+  const int len = pu ? c->mix_len : na;
+  double* x_in = pu ? c->mix_in : c->dq_in;
+  double* x_out = pu ? c->mix_out : c->dq;
+  double* hx = pu ? c->mix_hx : c->hx;
+  double* hf = pu ? c->mix_hf : c->hf;
+  HIPCHK(c, hipMemsetAsync(x_in, 0, sizeof(double) * len, c->stream));
   double res = INFINITY;
   int it;
   for (it = 1; it <= c->opt.scc_maxiter; ++it) {
-    HIPCHK(c, td::potential(c->stream, c->gamma, c->dq_in, c->pos, nullptr, c->orb_off, na, c->v,
+    HIPCHK(c, td::potential(c->stream, c->gamma, x_in, c->pos, nullptr, c->orb_off, na, c->v,
                             c->vorb));
-    HIPCHK(c, td::assemble_h(c->stream, c->H0, c->S, c->vorb, c->H, np));
+    assemble_hamiltonian(c, pu ? x_in + na : nullptr);
     purify(c);
     mulliken(c, c->scal + SC_MU);
+    if (pu) {
+      HIPCHK(c, hipMemcpyAsync(x_out, c->dq, sizeof(double) * na, hipMemcpyDeviceToDevice,
+                               c->stream));
+      block_pops(c, x_out + na);
+    }
     const int count = std::min(it, m), slot = (it - 1) % m;
-    HIPCHK(c, td::anderson_mix(c->stream, c->dq_in, c->dq, c->hx, c->hf, na, m, count, slot,
+    HIPCHK(c, td::anderson_mix(c->stream, x_in, x_out, hx, hf, len, m, count, slot,
                                c->opt.mix_beta, c->scal + SC_RES));
     read_scal(c, SC_RES, &res, 1);
     REQUIRE(c, std::isfinite(res), TD_ESCF, "SCC cycle produced non-finite charges");
@@ -265,6 +283,30 @@ bool finite_all(const double* p, size_t n) {
   return true;
 }
 
+// Shells of the on-site corrections: contiguous, covering all orbitals,
+// each of 1..TD_PLUS_U_MAX_SHELL orbitals of one atom, finite U >= 0.
+void validate_plus_u(td_ctx* c, const td_system* s) {
+  REQUIRE(c, s->plus_u == TD_PLUS_U_NONE || s->plus_u == TD_PLUS_U_FLL ||
+                 s->plus_u == TD_PLUS_U_PSIC,
+          TD_EINVAL, "unknown plus_u");
+  if (s->plus_u == TD_PLUS_U_NONE) return;
+  REQUIRE(c, s->n_shells > 0 && s->n_shells <= s->n_orb && s->shell_offset && s->shell_u,
+          TD_EINVAL, "plus_u needs n_shells, shell_offset and shell_u");
+  REQUIRE(c, s->shell_offset[0] == 0 && s->shell_offset[s->n_shells] == s->n_orb, TD_EINVAL,
+          "shell_offset must start at 0 and end at n_orb");
+  int a = 0;
+  for (int b = 0; b < s->n_shells; ++b) {
+    const int lo = s->shell_offset[b], hi = s->shell_offset[b + 1];
+    REQUIRE(c, hi > lo && hi - lo <= TD_PLUS_U_MAX_SHELL, TD_EINVAL,
+            "every shell needs 1 to TD_PLUS_U_MAX_SHELL orbitals");
+    while (a < s->n_atoms && s->orb_offset[a + 1] <= lo) ++a;
+    REQUIRE(c, a < s->n_atoms && s->orb_offset[a] <= lo && hi <= s->orb_offset[a + 1], TD_EINVAL,
+            "a shell must lie within one atom");
+    REQUIRE(c, std::isfinite(s->shell_u[b]) && s->shell_u[b] >= 0.0, TD_EINVAL,
+            "shell_u must be finite and >= 0");
+  }
+}
+
 void validate(td_ctx* c, const td_system* s, const td_options* o) {
   REQUIRE(c, s && o, TD_EINVAL, "null system or options");
   REQUIRE(c, s->n_atoms > 0 && s->n_orb > 0, TD_EINVAL, "n_atoms and n_orb must be positive");
@@ -295,6 +337,9 @@ void validate(td_ctx* c, const td_system* s, const td_options* o) {
   REQUIRE(c, o->dt > 0 && std::isfinite(o->dt), TD_EINVAL, "dt must be positive");
   REQUIRE(c, o->precision == TD_FP64 || o->precision == TD_SPLIT_BF16, TD_EINVAL,
           "unknown precision");
+  validate_plus_u(c, s);
+  REQUIRE(c, s->plus_u == TD_PLUS_U_NONE || o->precision == TD_FP64, TD_ENOTSUP,
+          "on-site corrections (plus_u) need TD_FP64");
   REQUIRE(c, o->precision == TD_FP64 || (o->n_slices >= 3 && o->n_slices <= 5), TD_EINVAL,
           "n_slices must be 3, 4 or 5");
   REQUIRE(c, o->scc_tol > 0 && o->scc_maxiter > 0 && o->mix_beta > 0 && o->mix_beta <= 1,
@@ -482,8 +527,8 @@ void upload_padded(td_ctx* c, const double* host, int n, double* dev, int np) {
 
 // Host copies of a model given by device pointers.
 struct HostModel {
-  std::vector<int32_t> orb_offset;
-  std::vector<double> positions, S, H0, gamma, q0, rho0, occ;
+  std::vector<int32_t> orb_offset, shell_offset;
+  std::vector<double> positions, S, H0, gamma, q0, rho0, occ, shell_u;
 };
 
 template <class T>
@@ -511,6 +556,9 @@ td_system host_view(td_ctx* c, const td_system* s, const td_options* o, HostMode
   fetch(c, st, s->q0, na, m.q0);
   if (s->rho0) fetch(c, st, s->rho0, 2 * n * n, m.rho0);
   if (s->occ) fetch(c, st, s->occ, n, m.occ);
+  const bool pu = s->plus_u != TD_PLUS_U_NONE && s->n_shells > 0 && s->n_shells <= s->n_orb;
+  if (pu && s->shell_offset) fetch(c, st, s->shell_offset, (size_t)s->n_shells + 1, m.shell_offset);
+  if (pu && s->shell_u) fetch(c, st, s->shell_u, (size_t)s->n_shells, m.shell_u);
   HIPCHK(c, hipStreamSynchronize(st));
   td_system h = *s;
   h.orb_offset = m.orb_offset.data();
@@ -521,8 +569,64 @@ td_system host_view(td_ctx* c, const td_system* s, const td_options* o, HostMode
   h.q0 = m.q0.data();
   h.rho0 = s->rho0 ? m.rho0.data() : nullptr;
   h.occ = s->occ ? m.occ.data() : nullptr;
+  h.shell_offset = (pu && s->shell_offset) ? m.shell_offset.data() : nullptr;
+  h.shell_u = (pu && s->shell_u) ? m.shell_u.data() : nullptr;
   h.flags = 0;
   return h;
+}
+
+// Device copies of the shells, the shell of every orbital (-1 in the
+// padding) and the buffers of the corrections and of their SCC mixing.
+void setup_plus_u(td_ctx* c, const td_system* s) {
+  const int nsh = s->n_shells, np = c->np;
+  constexpr int BS = td::kPlusUMaxShell * td::kPlusUMaxShell;
+  c->plus_u = s->plus_u;
+  c->nsh = nsh;
+  c->max_shell = 0;
+  std::vector<int> of(np, -1);
+  for (int b = 0; b < nsh; ++b) {
+    c->max_shell = std::max(c->max_shell, s->shell_offset[b + 1] - s->shell_offset[b]);
+    for (int u = s->shell_offset[b]; u < s->shell_offset[b + 1]; ++u) of[u] = b;
+  }
+  HIPCHK(c, hipMalloc((void**)&c->sh_off, sizeof(int) * (nsh + 1)));
+  HIPCHK(c, hipMalloc((void**)&c->sh_of, sizeof(int) * np));
+  HIPCHK(c, hipMemcpyAsync(c->sh_off, s->shell_offset, sizeof(int) * (nsh + 1),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->sh_of, of.data(), sizeof(int) * np, hipMemcpyHostToDevice,
+                           c->stream));
+  dalloc(c, &c->sh_u, nsh);
+  HIPCHK(c, hipMemcpyAsync(c->sh_u, s->shell_u, sizeof(double) * nsh, hipMemcpyHostToDevice,
+                           c->stream));
+  dalloc(c, &c->sh_n, (size_t)nsh * BS);
+  dalloc(c, &c->sh_v, (size_t)nsh * BS);
+  dalloc(c, &c->sh_e, nsh);
+  c->mix_len = c->na + nsh * BS;
+  dalloc(c, &c->mix_in, c->mix_len);
+  dalloc(c, &c->mix_out, c->mix_len);
+  dalloc(c, &c->mix_hx, (size_t)8 * c->mix_len);
+  dalloc(c, &c->mix_hf, (size_t)8 * c->mix_len);
+  sync(c);   // `of` is a pageable staging buffer: finish its copy before it goes
+}
+
+// H of the current potential (c->vorb) plus, with on-site corrections, the
+// term of the block populations n (device, shell blocks): V from n, then
+// the assembly.
+void assemble_hamiltonian(td_ctx* c, const double* n_blocks) {
+  if (c->plus_u == TD_PLUS_U_NONE) {
+    HIPCHK(c, td::assemble_h(c->stream, c->H0, c->S, c->vorb, c->H, c->np));
+    return;
+  }
+  HIPCHK(c, td::plus_u_potential(c->stream, n_blocks, c->sh_off, c->sh_u, c->nsh, c->plus_u,
+                                 c->sh_v));
+  HIPCHK(c, td::assemble_h_plus_u(c->stream, c->H0, c->S, c->vorb, c->sh_of, c->sh_off, c->sh_v,
+                                  c->H, c->np));
+}
+
+// Block populations of the current density into `out` (and the shells'
+// correction energies into sh_e).
+void block_pops(td_ctx* c, double* out) {
+  HIPCHK(c, td::block_populations(c->stream, c->rho_cur, 2 * c->np, c->S, c->np, c->sh_off,
+                                  c->sh_u, c->nsh, c->max_shell, c->plus_u, c->np, out, c->sh_e));
 }
 
 void create_impl(td_ctx* c, const td_system* s_in, const td_options* o) {
@@ -598,6 +702,7 @@ void create_impl(td_ctx* c, const td_system* s_in, const td_options* o) {
                            c->stream));
   upload_padded(c, s->S, n, c->S, np);
   upload_padded(c, s->H0, n, c->H0, np);
+  if (s->plus_u != TD_PLUS_U_NONE) setup_plus_u(c, s);
   c->info.n_atoms = na;
   c->info.n_orb = n;
   c->info.n_pad = np;
@@ -752,7 +857,8 @@ void step_impl(td_ctx* c, int nsteps, const double* field) {
       split_products(c, Ek, e);
     } else {
       HIPCHK(c, td::potential(st, c->gamma, c->dq, c->pos, Ek, c->orb_off, na, c->v, c->vorb));
-      HIPCHK(c, td::assemble_h(st, c->H0, c->S, c->vorb, c->H, np));
+      if (c->plus_u != TD_PLUS_U_NONE) block_pops(c, c->sh_n);
+      assemble_hamiltonian(c, c->sh_n);
       if (prof) HIPCHK(c, hipEventRecord(e[1], st));
       // X = S^-1 H rho (Eq. 10), as A = S^-1 H then A [Re rho | Im rho]
       gemm(c, 1, np, np, np, 1.0, c->Sinv, np, c->H, np, c->A, np);
@@ -964,6 +1070,8 @@ void create_ehr_impl(td_ctx* c, const td_system* s, const td_model* m, const dou
           "moving-nuclei contexts take host pointers");
   validate_model(c, s, m);
   REQUIRE(c, o->precision == TD_FP64, TD_ENOTSUP, "moving nuclei run in TD_FP64 precision only");
+  REQUIRE(c, s->plus_u == TD_PLUS_U_NONE, TD_ENOTSUP,
+          "moving nuclei have no on-site corrections (plus_u)");
   if (vel) REQUIRE(c, finite_all(vel, 3 * (size_t)s->n_atoms), TD_EINVAL, "non-finite velocities");
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
@@ -1127,7 +1235,17 @@ td_status td_get_energy(td_ctx* ctx, const double field[3], double* energy) {
                                field ? c->scal + SC_FIELD : nullptr, c->na, c->scal + SC_E));
     double e[3];
     read_scal(c, SC_E, e, 3);
-    *energy = e[0] + e[1] + e[2];
+    double e_u = 0.0;
+    if (c->plus_u != TD_PLUS_U_NONE) {
+      // correction energy (Sec. 3.2, Eq. 21 or 24) of the current density
+      block_pops(c, c->sh_n);
+      std::vector<double> es(c->nsh);
+      HIPCHK(c, hipMemcpyAsync(es.data(), c->sh_e, sizeof(double) * c->nsh,
+                               hipMemcpyDeviceToHost, c->stream));
+      sync(c);
+      for (double x : es) e_u += x;
+    }
+    *energy = e[0] + e[1] + e[2] + e_u;
   });
 }
 

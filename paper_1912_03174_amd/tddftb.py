@@ -21,6 +21,8 @@ TD_ESCF, TD_EUNSTABLE, TD_ENOTSUP, TD_ESTATE = -5, -6, -7, -8
 TD_FP64, TD_SPLIT_BF16 = 0, 1
 TD_KT_GEMM_SH, TD_KT_GEMM_ARHO, TD_KT_UPDATE, TD_KT_OTHER = 0, 1, 2, 3
 TD_DEVICE_PTRS = 1
+TD_PLUS_U_NONE, TD_PLUS_U_FLL, TD_PLUS_U_PSIC = 0, 1, 2
+TD_PLUS_U_MAX_SHELL = 7
 
 EXPORTED = [
     "td_default_options", "td_create", "td_kick", "td_step", "td_get_charges",
@@ -43,7 +45,8 @@ class TdSystem(ctypes.Structure):
     _fields_ = [("n_atoms", ctypes.c_int32), ("n_orb", ctypes.c_int32),
                 ("orb_offset", _ip), ("positions", _dp), ("S", _dp), ("H0", _dp),
                 ("gamma", _dp), ("q0", _dp), ("n_elec", ctypes.c_int32), ("rho0", _dp),
-                ("occ", _dp), ("flags", ctypes.c_uint32)]
+                ("occ", _dp), ("flags", ctypes.c_uint32), ("plus_u", ctypes.c_int32),
+                ("n_shells", ctypes.c_int32), ("shell_offset", _ip), ("shell_u", _dp)]
 
 
 class TdOptions(ctypes.Structure):
@@ -230,8 +233,20 @@ def td_create_from_tensors(orb_offset, positions, S, H0, gamma, q0, n_elec: int 
     return _create(s, opt)
 
 
-def _host_system(system, rho0=None, occ=None):
-    """TdSystem over host copies of `system`'s arrays (kept alive in the result's _keep)."""
+def _plus_u_mode(mode) -> int:
+    """'fll' / 'psic', or an integer passed through for the library to check."""
+    if isinstance(mode, (int, np.integer)):
+        return int(mode)
+    names = {"fll": TD_PLUS_U_FLL, "psic": TD_PLUS_U_PSIC}
+    if mode not in names:
+        raise ValueError(f"unknown plus_u mode {mode!r}")
+    return names[mode]
+
+
+def _host_system(system, rho0=None, occ=None, plus_u=None):
+    """TdSystem over host copies of `system`'s arrays (kept alive in the result's _keep).
+    ``plus_u``: None, or an object with ``mode`` ('fll' / 'psic' or TD_PLUS_U_*),
+    ``shell_offset`` and ``shell_u`` (the on-site corrections)."""
     keep = _Keep()
     keep.off = np.ascontiguousarray(system.orb_offset, dtype=np.int32)
     keep.pos = _f64(system.positions)
@@ -247,20 +262,27 @@ def _host_system(system, rho0=None, occ=None):
                  n_elec=int(system.n_elec) if occ is None else 0,
                  rho0=None if keep.rho0 is None else keep.rho0.ctypes.data_as(_dp),
                  occ=_ptr(keep.occ), flags=0)
+    if plus_u is not None:
+        keep.shell_off = np.ascontiguousarray(plus_u.shell_offset, dtype=np.int32)
+        keep.shell_u = _f64(plus_u.shell_u)
+        s.plus_u = _plus_u_mode(plus_u.mode)
+        s.n_shells = len(keep.shell_u)
+        s.shell_offset = _ptr(keep.shell_off, np.int32)
+        s.shell_u = _ptr(keep.shell_u)
     s._keep = keep
     return s
 
 
 def td_create(system, options: Optional[TdOptions] = None, rho0: Optional[np.ndarray] = None,
-              occ: Optional[np.ndarray] = None):
+              occ: Optional[np.ndarray] = None, plus_u=None):
     """td_create: returns an opaque context handle (c_void_p)."""
-    return _create(_host_system(system, rho0, occ), options)
+    return _create(_host_system(system, rho0, occ, plus_u), options)
 
 
 def td_create_ehrenfest(system, model: dict, velocities=None, options: Optional[TdOptions] = None,
-                        rho0: Optional[np.ndarray] = None):
+                        rho0: Optional[np.ndarray] = None, plus_u=None):
     """td_create_ehrenfest over host arrays; ``model`` as workloads.two_centre_model."""
-    hs = _host_system(system, rho0)
+    hs = _host_system(system, rho0, None, plus_u)
     keep = _Keep()
     keep.species = np.ascontiguousarray(model["species"], dtype=np.int32)
     keep.norb = np.ascontiguousarray(model["species_norb"], dtype=np.int32)
@@ -307,11 +329,13 @@ def _bcheck(b, st):
         raise TdError(st, load().td_batch_last_error(b).decode())
 
 
-def td_batch_create(systems, options: Optional[TdOptions] = None, rho0s=None, flags: int = 0):
-    """td_batch_create over host arrays; rho0s: None or a list (entries may be None)."""
+def td_batch_create(systems, options: Optional[TdOptions] = None, rho0s=None, flags: int = 0,
+                    plus_us=None):
+    """td_batch_create over host arrays; rho0s, plus_us: None or lists (entries may be None)."""
     n = len(systems)
     rho0s = rho0s if rho0s is not None else [None] * n
-    hs = [_host_system(s, r) for s, r in zip(systems, rho0s)]
+    plus_us = plus_us if plus_us is not None else [None] * n
+    hs = [_host_system(s, r, None, u) for s, r, u in zip(systems, rho0s, plus_us)]
     arr = (TdSystem * n)(*hs)
     opt = options if options is not None else td_default_options()
     b = ctypes.c_void_p()
@@ -487,7 +511,7 @@ class Propagator:
 
     def __init__(self, system, dt=0.2, precision=TD_FP64, n_slices=4, rho0=None, occ=None,
                  profile=False,
-                 scc_tol=1e-12, scc_maxiter=300):
+                 scc_tol=1e-12, scc_maxiter=300, plus_u=None):
         opt = td_default_options()
         opt.dt = dt
         opt.precision = precision
@@ -497,7 +521,7 @@ class Propagator:
         opt.scc_maxiter = scc_maxiter
         self.n_atoms = len(system.q0)
         self.n_orb = int(system.orb_offset[-1])
-        self.ctx = td_create(system, opt, rho0=rho0, occ=occ)
+        self.ctx = td_create(system, opt, rho0=rho0, occ=occ, plus_u=plus_u)
 
     def kick(self, e0, direction):
         td_kick(self.ctx, e0, direction)

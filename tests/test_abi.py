@@ -156,3 +156,46 @@ def test_ehrenfest_arguments_rejected_before_device(T):
     with pytest.raises(T.TdError) as e:
         T.td_create_ehrenfest(s, dict(m, species=np.zeros(s.n_atoms, dtype=np.int32)))
     assert e.value.status == T.TD_EINVAL
+
+
+class _PU:
+    def __init__(self, mode, shell_offset, shell_u):
+        self.mode, self.shell_offset, self.shell_u = mode, shell_offset, shell_u
+
+
+def test_plus_u_arguments_rejected_before_device(T):
+    s = W.flake_c24h16()
+    off, u = W.atomic_shells(s, {("C", "p"): 0.2})
+
+    def status(pu, **kw):
+        with pytest.raises(T.TdError) as e:
+            T.td_create(s, kw.get("opt"), plus_u=pu)
+        return e.value.status
+
+    # a shell spanning two atoms, a shell of 8 orbitals, negative or
+    # non-finite U, offsets not ending at n_orb, an unknown mode
+    assert list(off[:5]) == [0, 1, 4, 5, 8]      # atom 0: s 0, p 1-3; atom 1: s 4, p 5-7
+    cross = np.array([0, 1, 3, 5] + off[4:].tolist(), dtype=np.int32)   # shell [3, 5)
+    assert status(_PU("fll", cross, np.zeros(len(cross) - 1))) == T.TD_EINVAL
+    big = np.array([0, 8, s.n_orb], dtype=np.int32)
+    assert status(_PU("fll", big, np.zeros(2))) == T.TD_EINVAL
+    neg = u.copy()
+    neg[1] = -0.1
+    assert status(_PU("fll", off, neg)) == T.TD_EINVAL
+    nan = u.copy()
+    nan[1] = np.nan
+    assert status(_PU("psic", off, nan)) == T.TD_EINVAL
+    assert status(_PU("fll", off[:-1], u[:-1])) == T.TD_EINVAL
+    assert status(_PU(7, off, u)) == T.TD_EINVAL
+    # not available with split-bf16 products, in batches or with moving nuclei
+    o = T.td_default_options()
+    o.precision = T.TD_SPLIT_BF16
+    assert status(_PU("fll", off, u), opt=o) == T.TD_ENOTSUP
+    with pytest.raises(T.TdError) as e:
+        T.td_batch_create([s, s], plus_us=[None, _PU("fll", off, u)])
+    assert e.value.status == T.TD_ENOTSUP
+    b = W.benzene()
+    boff, bu = W.atomic_shells(b, {("C", "p"): 0.2})
+    with pytest.raises(T.TdError) as e:
+        T.td_create_ehrenfest(b, W.two_centre_model(b), plus_u=_PU("psic", boff, bu))
+    assert e.value.status == T.TD_ENOTSUP
