@@ -82,8 +82,8 @@ typedef enum {
  *   FLL:  dE = sum_b -(U_b / 4) sum_uv n_uv^2 + (U_b / 2) sum_u n_uu
  *   pSIC: dE = sum_b -(U_b / 4) sum_uv n_uv^2
  * and its derivative V_b = -(U_b / 2) (n_b - 1) (FLL) or -(U_b / 2) n_b
- * (pSIC) enters H as 1/2 (S V + V S), V block diagonal. FP64 contexts
- * only: TD_SPLIT_BF16, batches and moving nuclei return TD_ENOTSUP. */
+ * (pSIC) enters H as 1/2 (S V + V S), V block diagonal. Batches and
+ * moving nuclei return TD_ENOTSUP. */
 #define TD_PLUS_U_NONE 0
 #define TD_PLUS_U_FLL 1
 #define TD_PLUS_U_PSIC 2

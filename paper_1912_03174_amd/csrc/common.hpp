@@ -195,6 +195,11 @@ hipError_t block_populations(hipStream_t s, const double* rho, int ldr, const do
                              int mode, int ncols, double* n_out, double* e_sh);
 hipError_t plus_u_potential(hipStream_t s, const double* n, const int* sh_off, const double* sh_u,
                             int nsh, int mode, double* V);
+// dV = -(U/2)(n - cs[0] nref) per shell block (change from the reference)
+hipError_t plus_u_delta_potential(hipStream_t s, const double* n, const double* nref,
+                                  const double* cs, const int* sh_off, const double* sh_u,
+                                  int nsh, double* V);
+// H0 may be null: the SCC and correction terms alone
 hipError_t assemble_h_plus_u(hipStream_t s, const double* H0, const double* S, const double* vorb,
                              const int* sh_of, const int* sh_off, const double* V, double* H,
                              int np);

@@ -30,6 +30,7 @@ struct td_ctx {
   int plus_u = 0, nsh = 0, max_shell = 0, mix_len = 0;
   int *sh_off = nullptr, *sh_of = nullptr;
   double *sh_u = nullptr, *sh_n = nullptr, *sh_v = nullptr, *sh_e = nullptr;
+  double* sh_nref = nullptr;   // split products: block populations of rho_ref
   double *mix_in = nullptr, *mix_out = nullptr, *mix_hx = nullptr, *mix_hf = nullptr;
   double* field = nullptr;
   int field_cap = 0;

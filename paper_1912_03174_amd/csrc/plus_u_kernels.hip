@@ -98,10 +98,27 @@ __global__ void k_plus_u_potential(const double* __restrict__ n, const int* __re
   V[idx] = x;
 }
 
+// Change of the potentials from the reference state (split products): the
+// populations are linear in rho, so for rho = rho_ref + delta - c rho_ref
+// (delta's populations n, the reference's nref, c the trace correction)
+// both modes give dV = -(U/2) (n - c nref).
+__global__ void k_plus_u_delta_potential(const double* __restrict__ n,
+                                         const double* __restrict__ nref,
+                                         const double* __restrict__ cs,
+                                         const int* __restrict__ sh_off,
+                                         const double* __restrict__ sh_u, int nsh,
+                                         double* __restrict__ V) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= nsh * BS) return;
+  const int b = idx / BS, r = idx % BS, u = r / MAXB, v = r % MAXB;
+  const int m = sh_off[b + 1] - sh_off[b];
+  V[idx] = (u < m && v < m) ? -0.5 * sh_u[b] * (n[idx] - cs[0] * nref[idx]) : 0.0;
+}
+
 // H = H0 + 1/2 S_rc (v_r + v_c) (Eqs. 6-7) + 1/2 (S V + V S)_rc with V the
 // block-diagonal shell potentials: (S V)_rc sums over the shell of c,
 // (V S)_rc over the shell of r. sh_of[u] = shell of orbital u (-1 in the
-// padding).
+// padding). H0 may be null (the change of H for split products).
 __global__ void k_assemble_h_u(const double* __restrict__ H0, const double* __restrict__ S,
                                const double* __restrict__ vorb, const int* __restrict__ sh_of,
                                const int* __restrict__ sh_off, const double* __restrict__ V,
@@ -109,7 +126,7 @@ __global__ void k_assemble_h_u(const double* __restrict__ H0, const double* __re
   const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= (size_t)np * np) return;
   const int r = (int)(idx / np), c = (int)(idx % np);
-  double h = H0[idx] + 0.5 * S[idx] * (vorb[r] + vorb[c]);
+  double h = (H0 ? H0[idx] : 0.0) + 0.5 * S[idx] * (vorb[r] + vorb[c]);
   double corr = 0.0;
   const int bc = sh_of[c];
   if (bc >= 0) {
@@ -151,6 +168,15 @@ hipError_t plus_u_potential(hipStream_t s, const double* n, const int* sh_off, c
   if (nsh <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_plus_u_potential, dim3(blocks_of((size_t)nsh * BS)), dim3(256), 0, s, n,
                      sh_off, sh_u, nsh, mode, V);
+  return hipGetLastError();
+}
+
+hipError_t plus_u_delta_potential(hipStream_t s, const double* n, const double* nref,
+                                  const double* cs, const int* sh_off, const double* sh_u,
+                                  int nsh, double* V) {
+  if (nsh <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_plus_u_delta_potential, dim3(blocks_of((size_t)nsh * BS)), dim3(256), 0, s,
+                     n, nref, cs, sh_off, sh_u, nsh, V);
   return hipGetLastError();
 }
 

@@ -70,6 +70,7 @@ void free_all(td_ctx* c) {
                       &c->GS, &c->GH, &c->W, &c->Dm, &c->Sinv_prev, &c->Z, &c->dgamma,
                       &c->vel, &c->F,
                       &c->e_kin, &c->e_el, &c->sh_u, &c->sh_n, &c->sh_v, &c->sh_e,
+                      &c->sh_nref,
                       &c->mix_in, &c->mix_out, &c->mix_hx, &c->mix_hf};
   for (double** b : ebufs) {
     if (*b) (void)hipFree(*b);
@@ -221,7 +222,7 @@ void purify(td_ctx* c) {
 }
 
 void assemble_hamiltonian(td_ctx* c, const double* n_blocks);
-void block_pops(td_ctx* c, double* out);
+void block_pops(td_ctx* c, double* out, const double* rho = nullptr, int ldr = 0);
 
 // With on-site corrections the mixed vector is [dq | block populations]:
 // H is built from the mixed charges and populations, and both are
@@ -338,8 +339,6 @@ void validate(td_ctx* c, const td_system* s, const td_options* o) {
   REQUIRE(c, o->precision == TD_FP64 || o->precision == TD_SPLIT_BF16, TD_EINVAL,
           "unknown precision");
   validate_plus_u(c, s);
-  REQUIRE(c, s->plus_u == TD_PLUS_U_NONE || o->precision == TD_FP64, TD_ENOTSUP,
-          "on-site corrections (plus_u) need TD_FP64");
   REQUIRE(c, o->precision == TD_FP64 || (o->n_slices >= 3 && o->n_slices <= 5), TD_EINVAL,
           "n_slices must be 3, 4 or 5");
   REQUIRE(c, o->scc_tol > 0 && o->scc_maxiter > 0 && o->mix_beta > 0 && o->mix_beta <= 1,
@@ -408,7 +407,11 @@ void split_init(td_ctx* c) {
                                c->scal + SC_MU, c->scal + SC_NE));
   HIPCHK(c, td::potential(st, c->gamma, c->dq, c->pos, nullptr, c->orb_off, na, c->v_ref,
                           c->vorb));
-  HIPCHK(c, td::assemble_h(st, c->H0, c->S, c->vorb, c->H, np));
+  if (c->plus_u != TD_PLUS_U_NONE) {
+    dalloc(c, &c->sh_nref, (size_t)c->nsh * td::kPlusUMaxShell * td::kPlusUMaxShell);
+    block_pops(c, c->sh_nref, c->rho_ref, np);
+  }
+  assemble_hamiltonian(c, c->sh_nref);     // H_ref, with the correction of rho_ref
   gemm(c, 0, np, np, np, 1.0, c->Sinv, np, c->H, np, c->Agsb, np);
   gemm(c, 0, np, np, np, 1.0, c->Agsb, np, c->rho_ref, np, c->Xref, 2 * np);
   td::SliceSrc si;
@@ -438,7 +441,20 @@ void split_products(td_ctx* c, const double* E, hipEvent_t* ev) {
   sdh.ld0 = np;
   sdh.v = c->vorb;
   const int S = c->ns;
-  slice(c, td::SLICE_DH, sdh, np, np, c->sl_dh, np * S, c->e_dh);
+  if (c->plus_u != TD_PLUS_U_NONE) {
+    // dH = 1/2 S o (dv + dv) + 1/2 (S dV + dV S) (Sec. 3.2) formed in A, then sliced
+    block_pops(c, c->sh_n);
+    HIPCHK(c, td::plus_u_delta_potential(st, c->sh_n, c->sh_nref, c->scal + SC_RENORM,
+                                         c->sh_off, c->sh_u, c->nsh, c->sh_v));
+    HIPCHK(c, td::assemble_h_plus_u(st, nullptr, c->S, c->vorb, c->sh_of, c->sh_off, c->sh_v,
+                                    c->A, np));
+    td::SliceSrc sa;
+    sa.M0 = c->A;
+    sa.ld0 = np;
+    slice(c, td::SLICE_PLAIN, sa, np, np, c->sl_dh, np * S, c->e_dh);
+  } else {
+    slice(c, td::SLICE_DH, sdh, np, np, c->sl_dh, np * S, c->e_dh);
+  }
   td::SplitGemm g1;
   g1.m = np;
   g1.n = np;
@@ -622,11 +638,15 @@ void assemble_hamiltonian(td_ctx* c, const double* n_blocks) {
                                   c->H, c->np));
 }
 
-// Block populations of the current density into `out` (and the shells'
-// correction energies into sh_e).
-void block_pops(td_ctx* c, double* out) {
-  HIPCHK(c, td::block_populations(c->stream, c->rho_cur, 2 * c->np, c->S, c->np, c->sh_off,
-                                  c->sh_u, c->nsh, c->max_shell, c->plus_u, c->np, out, c->sh_e));
+// Block populations of a density (default: the current one, wide) into
+// `out`, and the shells' correction energies into sh_e.
+void block_pops(td_ctx* c, double* out, const double* rho, int ldr) {
+  if (!rho) {
+    rho = c->rho_cur;
+    ldr = 2 * c->np;
+  }
+  HIPCHK(c, td::block_populations(c->stream, rho, ldr, c->S, c->np, c->sh_off, c->sh_u, c->nsh,
+                                  c->max_shell, c->plus_u, c->np, out, c->sh_e));
 }
 
 void create_impl(td_ctx* c, const td_system* s_in, const td_options* o) {
@@ -1238,7 +1258,12 @@ td_status td_get_energy(td_ctx* ctx, const double field[3], double* energy) {
     double e_u = 0.0;
     if (c->plus_u != TD_PLUS_U_NONE) {
       // correction energy (Sec. 3.2, Eq. 21 or 24) of the current density
-      block_pops(c, c->sh_n);
+      if (c->split) {
+        full_density(c, c->rho_cur, c->stage);
+        block_pops(c, c->sh_n, c->stage, 2 * c->np);
+      } else {
+        block_pops(c, c->sh_n);
+      }
       std::vector<double> es(c->nsh);
       HIPCHK(c, hipMemcpyAsync(es.data(), c->sh_e, sizeof(double) * c->nsh,
                                hipMemcpyDeviceToHost, c->stream));

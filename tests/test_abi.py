@@ -187,10 +187,7 @@ def test_plus_u_arguments_rejected_before_device(T):
     assert status(_PU("psic", off, nan)) == T.TD_EINVAL
     assert status(_PU("fll", off[:-1], u[:-1])) == T.TD_EINVAL
     assert status(_PU(7, off, u)) == T.TD_EINVAL
-    # not available with split-bf16 products, in batches or with moving nuclei
-    o = T.td_default_options()
-    o.precision = T.TD_SPLIT_BF16
-    assert status(_PU("fll", off, u), opt=o) == T.TD_ENOTSUP
+    # not available in batches or with moving nuclei
     with pytest.raises(T.TdError) as e:
         T.td_batch_create([s, s], plus_us=[None, _PU("fll", off, u)])
     assert e.value.status == T.TD_ENOTSUP

@@ -2,7 +2,8 @@
 through the C ABI, against the CPU oracle (``oracle.plus_u``).
 
 Tolerances as for the SCC path: charges and densities to 1e-9 / 1e-12,
-dipole relative error 1e-10 over the run, energies to 1e-10.
+dipole relative error 1e-10 over the run, energies to 1e-10 (FP64);
+split-bf16 products: dipole relative error 1e-6.
 """
 import sys
 
@@ -95,6 +96,32 @@ def test_laser_run_matches_oracle(flake, ground):
     say(f"dipole relative error {err:.3e}")
     assert err < 1e-10
     p.close()
+
+
+@pytest.mark.parametrize("mode", [U.FLL, U.PSIC])
+def test_split_bf16_kicked_run(flake, ground, mode):
+    """Split-bf16 products with the correction in the change of H from the
+    reference: within the split path's 1e-6 dipole bound of the FP64 oracle."""
+    T = _T()
+    s = flake
+    pu, g = ground[mode]
+    say(f"plus_u split run {mode}")
+    Sinv = O.inverse_overlap(s.S)
+    rk = O.kick(g.rho, s.S, Sinv, s.positions, s.orb_offset, 1e-3, (1.0, 0.0, 0.0))
+    rho, _, mus, _ = U.propagate(s, pu, rk, 500, 0.2, Sinv=Sinv)
+    p = T.Propagator(s, rho0=g.rho, plus_u=pu, precision=T.TD_SPLIT_BF16, n_slices=4)
+    p.kick(1e-3, (1.0, 0.0, 0.0))
+    mu = p.step(500)
+    err = np.abs(mu - mus).max() / np.abs(mus - mus[0]).max()
+    say(f"split dipole relative error {err:.3e}")
+    assert err < 1e-6
+    assert abs(p.energy() - U.energy(s, rho, pu)) < 1e-6 * abs(U.energy(s, rho, pu))
+    # and the split ground state stays put
+    q = T.Propagator(s, rho0=g.rho, plus_u=pu, precision=T.TD_SPLIT_BF16, n_slices=4)
+    m0 = q.step(100)
+    assert np.abs(m0 - m0[0]).max() < 1e-10 * max(1.0, np.abs(m0[0]).max())
+    p.close()
+    q.close()
 
 
 def test_zero_u_is_bitwise_the_plain_path(flake, ground):
