@@ -132,29 +132,59 @@ __global__ __launch_bounds__(256) void k_b_leapfrog(const BatchMember* __restric
   const int tr = t >> 3, tc = (t & 7) * 4;
   const bool diag = (bi == bj);
   const int nt = diag ? 1 : 2;
-  for (int p = 0; p < nt; ++p) {
-    const int ti = p ? bj : bi, tj = p ? bi : bj;
-    const size_t g = (size_t)(ti * TS + tr) * ld + tj * TS + tc;
+  // every read (both X tiles and rho_{n-1}) before the first write: the
+  // update is in place, so the compiler could not reorder them itself
+  double2 xr[2][2], xi[2][2], br[2][2], bm[2][2];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      sre[p][tr][tc + c] = xre[g + c];
-      sim[p][tr][tc + c] = xim[g + c];
+  for (int p = 0; p < 2; ++p) {
+    if (p < nt) {
+      const int ti = p ? bj : bi, tj = p ? bi : bj;
+      const size_t g = (size_t)(ti * TS + tr) * ld + tj * TS + tc;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        xr[p][h] = *reinterpret_cast<const double2*>(xre + g + 2 * h);
+        xi[p][h] = *reinterpret_cast<const double2*>(xim + g + 2 * h);
+        br[p][h] = *reinterpret_cast<const double2*>(bre + g + 2 * h);
+        bm[p][h] = *reinterpret_cast<const double2*>(bim + g + 2 * h);
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    if (p < nt) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        sre[p][tr][tc + 2 * h] = xr[p][h].x;
+        sre[p][tr][tc + 2 * h + 1] = xr[p][h].y;
+        sim[p][tr][tc + 2 * h] = xi[p][h].x;
+        sim[p][tr][tc + 2 * h + 1] = xi[p][h].y;
+      }
     }
   }
   __syncthreads();
-  for (int p = 0; p < nt; ++p) {
-    const int ti = p ? bj : bi, tj = p ? bi : bj;
-    const int q = diag ? 0 : (p ^ 1);
-    const size_t go = (size_t)(ti * TS + tr) * ld + tj * TS + tc;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int cc = tc + c;
-      const double are = sre[p][tr][cc], aret = sre[q][cc][tr];
-      const double aim = sim[p][tr][cc], aimt = sim[q][cc][tr];
-      const double dre = aim + aimt;
-      const double dim = aret - are;
-      ore[go + c] = bre[go + c] + f * dre;
-      oim[go + c] = bim[go + c] + f * dim;
+  for (int p = 0; p < 2; ++p) {
+    if (p < nt) {
+      const int ti = p ? bj : bi, tj = p ? bi : bj;
+      const int q = diag ? 0 : (p ^ 1);
+      const size_t go = (size_t)(ti * TS + tr) * ld + tj * TS + tc;
+      double r[4], m[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int cc = tc + c;
+        const double are = sre[p][tr][cc], aret = sre[q][cc][tr];
+        const double aim = sim[p][tr][cc], aimt = sim[q][cc][tr];
+        const double dre = aim + aimt;
+        const double dim = aret - are;
+        const double b_re = (c & 1) ? br[p][c >> 1].y : br[p][c >> 1].x;
+        const double b_im = (c & 1) ? bm[p][c >> 1].y : bm[p][c >> 1].x;
+        r[c] = b_re + f * dre;
+        m[c] = b_im + f * dim;
+      }
+      *reinterpret_cast<double2*>(ore + go) = make_double2(r[0], r[1]);
+      *reinterpret_cast<double2*>(ore + go + 2) = make_double2(r[2], r[3]);
+      *reinterpret_cast<double2*>(oim + go) = make_double2(m[0], m[1]);
+      *reinterpret_cast<double2*>(oim + go + 2) = make_double2(m[2], m[3]);
     }
   }
 }
