@@ -166,12 +166,14 @@ hipError_t assemble_h(hipStream_t s, const double* H0, const double* S, const do
 
 // Transpose-pair passes over np x np tiles (np multiple of 32):
 //  leapfrog:   out = base + f * rhodot with rhodot = -i (X - X^+),
-//              X = Xre + i Xim:  Re rhodot = Xim + Xim^T,  Im rhodot = Xre^T - Xre
+//              X = Xre + i Xim:  Re rhodot = Xim + Xim^T,  Im rhodot = Xre^T - Xre;
+//              with xref (leading dimension ldr), Xre = xre + xref
 //  herm:       out = (T + T^+) / 2
 //  sym:        out_re = (T + T^T) / 2 (real), out_im = 0 when given
 hipError_t pair_leapfrog(hipStream_t s, const double* xre, const double* xim, int ldx,
                          const double* bre, const double* bim, int ldb, double* ore,
-                         double* oim, int ldo, int np, double f);
+                         double* oim, int ldo, int np, double f, const double* xref = nullptr,
+                         int ldr = 0);
 hipError_t pair_herm(hipStream_t s, const double* tre, const double* tim, int ldt,
                      double* ore, double* oim, int ldo, int np);
 hipError_t pair_sym(hipStream_t s, const double* t, int ldt, double* ore, double* oim,

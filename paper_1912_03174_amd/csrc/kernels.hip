@@ -119,10 +119,13 @@ enum { PAIR_LEAPFROG = 0, PAIR_HERM = 1, PAIR_SYM = 2 };
 // addend b of the leapfrog) is issued before its first write: the output
 // may alias b or x (in-place update), and reads then stores in program order
 // keep the loads in flight together instead of one round trip per store.
+// For PAIR_LEAPFROG, xref (optional, leading dimension ldr) is a real
+// addend of X: Re X = xre + xref.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_pair(const double* xre, const double* xim, int ldx,
                                               const double* bre, const double* bim, int ldb,
-                                              double* ore, double* oim, int ldo, double f) {
+                                              double* ore, double* oim, int ldo, double f,
+                                              const double* xref, int ldr) {
   const int bi = blockIdx.y, bj = blockIdx.x;
   if (bi > bj) return;
   __shared__ double sre[2][TS][TLD];   // [0]: tile (bi,bj), [1]: tile (bj,bi)
@@ -131,7 +134,7 @@ __global__ __launch_bounds__(256) void k_pair(const double* xre, const double* x
   const int tr = t >> 3, tc = (t & 7) * 4;
   const bool diag = (bi == bj);
   const int nt = diag ? 1 : 2;
-  double2 xr[2][2], xi[2][2], br[2][2], bm[2][2];
+  double2 xr[2][2], xi[2][2], br[2][2], bm[2][2], xf[2][2];
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
     if (p < nt) {
@@ -139,6 +142,11 @@ __global__ __launch_bounds__(256) void k_pair(const double* xre, const double* x
       const size_t g = (size_t)(ti * TS + tr) * ldx + tj * TS + tc;
       xr[p][0] = *reinterpret_cast<const double2*>(xre + g);
       xr[p][1] = *reinterpret_cast<const double2*>(xre + g + 2);
+      if (MODE == PAIR_LEAPFROG && xref) {
+        const size_t gr = (size_t)(ti * TS + tr) * ldr + tj * TS + tc;
+        xf[p][0] = *reinterpret_cast<const double2*>(xref + gr);
+        xf[p][1] = *reinterpret_cast<const double2*>(xref + gr + 2);
+      }
       if (MODE != PAIR_SYM) {
         xi[p][0] = *reinterpret_cast<const double2*>(xim + g);
         xi[p][1] = *reinterpret_cast<const double2*>(xim + g + 2);
@@ -157,6 +165,10 @@ __global__ __launch_bounds__(256) void k_pair(const double* xre, const double* x
     if (p < nt) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
+        if (MODE == PAIR_LEAPFROG && xref) {
+          xr[p][h].x = xr[p][h].x + xf[p][h].x;
+          xr[p][h].y = xr[p][h].y + xf[p][h].y;
+        }
         sre[p][tr][tc + 2 * h] = xr[p][h].x;
         sre[p][tr][tc + 2 * h + 1] = xr[p][h].y;
         if (MODE != PAIR_SYM) {
@@ -602,11 +614,11 @@ hipError_t assemble_h(hipStream_t s, const double* H0, const double* S, const do
 
 hipError_t pair_leapfrog(hipStream_t s, const double* xre, const double* xim, int ldx,
                          const double* bre, const double* bim, int ldb, double* ore, double* oim,
-                         int ldo, int np, double f) {
+                         int ldo, int np, double f, const double* xref, int ldr) {
   if (np % TS) return hipErrorInvalidValue;
   const dim3 grid(np / TS, np / TS);
   hipLaunchKernelGGL(k_pair<PAIR_LEAPFROG>, grid, dim3(256), 0, s, xre, xim, ldx, bre, bim, ldb,
-                     ore, oim, ldo, f);
+                     ore, oim, ldo, f, xref, ldr);
   return hipGetLastError();
 }
 
@@ -615,7 +627,8 @@ hipError_t pair_herm(hipStream_t s, const double* tre, const double* tim, int ld
   if (np % TS) return hipErrorInvalidValue;
   const dim3 grid(np / TS, np / TS);
   hipLaunchKernelGGL(k_pair<PAIR_HERM>, grid, dim3(256), 0, s, tre, tim, ldt,
-                     (const double*)nullptr, (const double*)nullptr, 0, ore, oim, ldo, 0.0);
+                     (const double*)nullptr, (const double*)nullptr, 0, ore, oim, ldo, 0.0,
+                     (const double*)nullptr, 0);
   return hipGetLastError();
 }
 
@@ -624,7 +637,8 @@ hipError_t pair_sym(hipStream_t s, const double* t, int ldt, double* ore, double
   if (np % TS) return hipErrorInvalidValue;
   const dim3 grid(np / TS, np / TS);
   hipLaunchKernelGGL(k_pair<PAIR_SYM>, grid, dim3(256), 0, s, t, (const double*)nullptr, ldt,
-                     (const double*)nullptr, (const double*)nullptr, 0, ore, oim, ldo, 0.0);
+                     (const double*)nullptr, (const double*)nullptr, 0, ore, oim, ldo, 0.0,
+                     (const double*)nullptr, 0);
   return hipGetLastError();
 }
 

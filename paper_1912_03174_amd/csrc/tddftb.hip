@@ -519,10 +519,8 @@ void split_products(td_ctx* c, const double* E, hipEvent_t* ev) {
   g2.k_hi = 2 * np;     // real columns: A delta_re + B rho_ref
   g2.k_lo = np;         // imaginary columns: A delta_im
   g2.n_split = np;
-  g2.C = c->X;
+  g2.C = c->X;            // without X_ref: the update adds it (real part only)
   g2.ldc = 2 * np;
-  g2.Cin = c->Xref;
-  g2.ldcin = 2 * np;
   if (ev) HIPCHK(c, hipEventRecord(ev[3], st));
   HIPCHK(c, td::split_gemm(st, c->ns, g2));
   if (ev) HIPCHK(c, hipEventRecord(ev[4], st));
@@ -888,13 +886,16 @@ void step_impl(td_ctx* c, int nsteps, const double* field) {
       if (prof) HIPCHK(c, hipEventRecord(e[4], st));
     }
     // rho_{k+1} = rho_{k-1} + 2 dt rhodot (Eq. 19); Euler start without history
+    // split products leave out X_ref = A_ref rho_ref (real); it is added here
+    const double* xref = c->split ? c->Xref : nullptr;
     if (c->has_prev) {
       HIPCHK(c, td::pair_leapfrog(st, c->X, c->X + np, 2 * np, c->rho_prev, c->rho_prev + np,
                                   2 * np, c->rho_prev, c->rho_prev + np, 2 * np, np,
-                                  2.0 * c->opt.dt));
+                                  2.0 * c->opt.dt, xref, 2 * np));
     } else {
       HIPCHK(c, td::pair_leapfrog(st, c->X, c->X + np, 2 * np, c->rho_cur, c->rho_cur + np,
-                                  2 * np, c->rho_prev, c->rho_prev + np, 2 * np, np, c->opt.dt));
+                                  2 * np, c->rho_prev, c->rho_prev + np, 2 * np, np, c->opt.dt,
+                                  xref, 2 * np));
       c->has_prev = true;
     }
     std::swap(c->rho_cur, c->rho_prev);
