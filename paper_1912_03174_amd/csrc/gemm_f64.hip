@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void dgemm_nn(const double* __restrict__ A, in
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
           const int row = m0 + wm * 64 + i * 16 + lk + 4 * rr;
-          C[(size_t)row * ldc + col] = alpha * acc[i][j][rr];
+          __builtin_nontemporal_store(alpha * acc[i][j][rr], &C[(size_t)row * ldc + col]);
         }
       }
   } else {

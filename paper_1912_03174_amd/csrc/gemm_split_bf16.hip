@@ -366,7 +366,7 @@ __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
       const int row = m0 + wm * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
       double v = acc64[j][e];
       if (p.Cin) v += p.Cin[(size_t)row * p.ldcin + col];
-      p.C[(size_t)row * p.ldc + col] = v;
+      __builtin_nontemporal_store(v, &p.C[(size_t)row * p.ldc + col]);   // streamed out
     }
   }
 }
