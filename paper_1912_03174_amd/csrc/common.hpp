@@ -100,12 +100,13 @@ struct ModelArgs {
   const int* species;      // [na]
   const int* norb;         // [nsp]: 1 or 4
   const int* orb_off;      // [na + 1]
+  const int* atom_of;      // [n]: atom of each orbital
   const double* sk_s;      // [nsp * nsp * 4]
   const double* sk_h;
   const double* scale_s;   // [na * na]
   const double* scale_h;
   const double* onsite;    // [nsp * 2]
-  int na, nsp;
+  int na, nsp, n;
   double decay;            // bohr
   double fd_step;          // central-difference step (bohr)
 };

@@ -9,6 +9,12 @@
 namespace td {
 namespace {
 
+// Component c (1..3) of the unit vector l, chosen by selects (no indexed
+// private array).
+__device__ inline double lcomp(const double* l, int c) {
+  return c == 1 ? l[0] : (c == 2 ? l[1] : l[2]);
+}
+
 // Element (i, j) of the two-centre block of atoms a (species sa) -> b
 // (species sb) with unit vector l from a to b and radial factor f;
 // orbital index 0 = s, 1..3 = p_x, p_y, p_z.
@@ -16,69 +22,91 @@ __device__ inline double sk_elem(const double* sk, int nsp, int sa, int sb, int 
                                  const double* l, double f) {
   const double* ab = sk + (sa * nsp + sb) * 4;
   if (i == 0 && j == 0) return ab[0] * f;
-  if (i == 0) return l[j - 1] * ab[1] * f;                       // s on a, p on b
-  if (j == 0) return -l[i - 1] * sk[(sb * nsp + sa) * 4 + 1] * f; // p on a, s on b
-  return (l[i - 1] * l[j - 1] * (ab[2] - ab[3]) + (i == j ? ab[3] : 0.0)) * f;
+  if (i == 0) return lcomp(l, j) * ab[1] * f;                       // s on a, p on b
+  if (j == 0) return -lcomp(l, i) * sk[(sb * nsp + sa) * 4 + 1] * f; // p on a, s on b
+  return (lcomp(l, i) * lcomp(l, j) * (ab[2] - ab[3]) + (i == j ? ab[3] : 0.0)) * f;
 }
 
-// Block of table `sk` between atoms a -> b displaced by d (bohr) into out[4][4].
-__device__ inline void sk_block(const double* sk, const double* scale, int na, int nsp, int a,
-                                int b, int sa, int sb, int oa, int ob, double decay,
-                                const double* d, double out[4][4]) {
+// Geometry of the pair a -> b displaced by d (bohr): unit vector l and the
+// radial factors of the S and H0 tables.
+struct PairGeom {
+  double l[3];
+  double fs, fh;
+};
+
+__device__ inline PairGeom pair_geom(const ModelArgs& m, size_t ab, const double* d) {
+  PairGeom g;
   const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-  const double l[3] = {d[0] / r, d[1] / r, d[2] / r};
-  const double f = exp(-r / decay) * scale[(size_t)a * na + b];
-  for (int i = 0; i < oa; ++i)
-    for (int j = 0; j < ob; ++j) out[i][j] = sk_elem(sk, nsp, sa, sb, i, j, l, f);
+  g.l[0] = d[0] / r;
+  g.l[1] = d[1] / r;
+  g.l[2] = d[2] / r;
+  const double e = exp(-r / m.decay);
+  g.fs = e * m.scale_s[ab];
+  g.fh = e * m.scale_h[ab];
+  return g;
 }
 
-// One thread per ordered atom pair (a, b): S, H0 blocks and, for a != b,
+// One thread per (row atom a, column orbital v), consecutive threads along
+// v: orbital v is orbital j of atom b; the thread writes column v of the
+// a -> b block (rows i < norb(a)) of S, H0 and, for a != b,
 // G[k] = (X(d + h e_k) - X(d - h e_k)) / 2h, d = R_b - R_a (the derivative
-// with respect to the column atom b).
+// with respect to the column atom b). Every row store is coalesced over v,
+// and the pair geometry is evaluated once per displacement for the column.
 __global__ void k_model(ModelArgs m, const double* __restrict__ pos, double* __restrict__ S,
                         double* __restrict__ H0, double* __restrict__ GS,
-                        double* __restrict__ GH, int np) {
+                        double* __restrict__ GH, int n, int np) {
   const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
-  const int na = m.na;
-  if (idx >= (size_t)na * na) return;
-  const int a = (int)(idx / na), b = (int)(idx % na);
+  if (idx >= (size_t)m.na * n) return;
+  const int a = (int)(idx / n), v = (int)(idx % n);
+  const int b = m.atom_of[v];
+  const int j = v - m.orb_off[b];
   const int sa = m.species[a], sb = m.species[b];
-  const int oa = m.norb[sa], ob = m.norb[sb];
-  const int ra = m.orb_off[a], cb = m.orb_off[b];
+  const int oa = m.norb[sa], ra = m.orb_off[a];
   const size_t nn = (size_t)np * np;
+  const size_t e0 = (size_t)ra * np + v;
   if (a == b) {
-    for (int i = 0; i < oa; ++i)
-      for (int j = 0; j < ob; ++j) {
-        const size_t e = (size_t)(ra + i) * np + cb + j;
-        S[e] = i == j ? 1.0 : 0.0;
-        H0[e] = i == j ? m.onsite[sa * 2 + (i > 0 ? 1 : 0)] : 0.0;
-        for (int k = 0; k < 3; ++k) {
-          GS[k * nn + e] = 0.0;
-          GH[k * nn + e] = 0.0;
-        }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i >= oa) break;
+      const size_t e = e0 + (size_t)i * np;
+      S[e] = i == j ? 1.0 : 0.0;
+      H0[e] = i == j ? m.onsite[sa * 2 + (i > 0 ? 1 : 0)] : 0.0;
+      for (int k = 0; k < 3; ++k) {
+        GS[k * nn + e] = 0.0;
+        GH[k * nn + e] = 0.0;
       }
+    }
     return;
   }
+  const size_t ab = (size_t)a * m.na + b;
   const double d[3] = {pos[3 * b] - pos[3 * a], pos[3 * b + 1] - pos[3 * a + 1],
                        pos[3 * b + 2] - pos[3 * a + 2]};
-  double blk[4][4], bp[4][4], bm[4][4];
-  for (int t = 0; t < 2; ++t) {
-    const double* sk = t ? m.sk_h : m.sk_s;
-    const double* sc = t ? m.scale_h : m.scale_s;
-    double* X = t ? H0 : S;
-    double* G = t ? GH : GS;
-    sk_block(sk, sc, na, m.nsp, a, b, sa, sb, oa, ob, m.decay, d, blk);
-    for (int i = 0; i < oa; ++i)
-      for (int j = 0; j < ob; ++j) X[(size_t)(ra + i) * np + cb + j] = blk[i][j];
-    for (int k = 0; k < 3; ++k) {
-      double dp[3] = {d[0], d[1], d[2]}, dm[3] = {d[0], d[1], d[2]};
-      dp[k] += m.fd_step;
-      dm[k] -= m.fd_step;
-      sk_block(sk, sc, na, m.nsp, a, b, sa, sb, oa, ob, m.decay, dp, bp);
-      sk_block(sk, sc, na, m.nsp, a, b, sa, sb, oa, ob, m.decay, dm, bm);
-      for (int i = 0; i < oa; ++i)
-        for (int j = 0; j < ob; ++j)
-          G[k * nn + (size_t)(ra + i) * np + cb + j] = (bp[i][j] - bm[i][j]) / (2.0 * m.fd_step);
+  {
+    const PairGeom g = pair_geom(m, ab, d);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i >= oa) break;
+      const size_t e = e0 + (size_t)i * np;
+      S[e] = sk_elem(m.sk_s, m.nsp, sa, sb, i, j, g.l, g.fs);
+      H0[e] = sk_elem(m.sk_h, m.nsp, sa, sb, i, j, g.l, g.fh);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double dp[3] = {d[0], d[1], d[2]}, dm[3] = {d[0], d[1], d[2]};
+    dp[k] += m.fd_step;
+    dm[k] -= m.fd_step;
+    const PairGeom gp = pair_geom(m, ab, dp), gm = pair_geom(m, ab, dm);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i >= oa) break;
+      const size_t e = k * nn + e0 + (size_t)i * np;
+      const double sp = sk_elem(m.sk_s, m.nsp, sa, sb, i, j, gp.l, gp.fs);
+      const double sm = sk_elem(m.sk_s, m.nsp, sa, sb, i, j, gm.l, gm.fs);
+      const double hp = sk_elem(m.sk_h, m.nsp, sa, sb, i, j, gp.l, gp.fh);
+      const double hm = sk_elem(m.sk_h, m.nsp, sa, sb, i, j, gm.l, gm.fh);
+      GS[e] = (sp - sm) / (2.0 * m.fd_step);
+      GH[e] = (hp - hm) / (2.0 * m.fd_step);
     }
   }
 }
@@ -197,8 +225,8 @@ unsigned nblocks(size_t n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t model_build(hipStream_t s, const ModelArgs& m, const double* pos, double* S,
                        double* H0, double* GS, double* GH, int np) {
-  hipLaunchKernelGGL(k_model, dim3(nblocks((size_t)m.na * m.na)), dim3(256), 0, s, m, pos, S, H0,
-                     GS, GH, np);
+  hipLaunchKernelGGL(k_model, dim3(nblocks((size_t)m.na * m.n)), dim3(256), 0, s, m, pos, S, H0,
+                     GS, GH, m.n, np);
   return hipGetLastError();
 }
 

@@ -171,8 +171,8 @@ template <int BT>
 __device__ __forceinline__ void dgemm_tile_body(const GemmProblem* __restrict__ pp, int local);
 
 template <int BT>
-__global__ __launch_bounds__(256) void dgemm_grouped_k(const GemmProblem* __restrict__ probs,
-                                                       int nprob, int ntiles) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BT == 64 ? 4 : 1)))
+void dgemm_grouped_k(const GemmProblem* __restrict__ probs, int nprob, int ntiles) {
   // XCD-aware order over the launch's tiles (a problem's tiles stay together).
   const int w = blockIdx.x;
   const int q = ntiles >> 3, r = ntiles & 7;
@@ -189,7 +189,8 @@ __global__ __launch_bounds__(256) void dgemm_grouped_k(const GemmProblem* __rest
 // One problem passed by value (no device table): the 64-tile form for
 // products with too few 128 x 128 tiles to fill the chip.
 template <int BT>
-__global__ __launch_bounds__(256) void dgemm_single_k(GemmProblem pr) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BT == 64 ? 4 : 1)))
+void dgemm_single_k(GemmProblem pr) {
   const int ntiles = pr.tiles_m * pr.tiles_n;
   const int w = blockIdx.x;
   const int q = ntiles >> 3, r = ntiles & 7;
@@ -236,68 +237,101 @@ __device__ __forceinline__ void dgemm_tile_body(const GemmProblem* __restrict__ 
 #pragma unroll
     for (int j = 0; j < FR; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  // staging registers (named, so they stay in VGPRs); ra2/3, rb2/3 unused for BT = 64
-  double2 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-#define TD_G_LOAD(kt)                                                          \
+  // Staging registers (named, so they stay in VGPRs; x2/x3 unused for
+  // BT = 64). 64-wide tiles use two sets: tile t of K is loaded into set
+  // t & 1 two compute stages before it is stored to LDS, so a global load has
+  // two stages of matrix-core work to arrive (one stage of a 64-wide tile is
+  // short). Prefetch indices are clamped to the last tile (a harmless
+  // reload) so the loop body is straight-line and each store waits only for
+  // the older set.
+  double2 pa0, pa1, pa2, pa3, pb0, pb1, pb2, pb3;
+  double2 qa0, qa1, qa2, qa3, qb0, qb1, qb2, qb3;
+#define TD_G_LOAD(P, kt)                                                       \
   do {                                                                         \
     const double* an_ = Ag + (size_t)(kt) * BK;                                \
     const double* bn_ = Bg + (size_t)(kt) * BK * ldb;                          \
-    ra0 = *reinterpret_cast<const double2*>(an_ + 0);                          \
-    ra1 = *reinterpret_cast<const double2*>(an_ + 2);                          \
-    rb0 = *reinterpret_cast<const double2*>(bn_ + 0);                          \
-    rb1 = *reinterpret_cast<const double2*>(bn_ + 2);                          \
+    P##a0 = *reinterpret_cast<const double2*>(an_ + 0);                        \
+    P##a1 = *reinterpret_cast<const double2*>(an_ + 2);                        \
+    P##b0 = *reinterpret_cast<const double2*>(bn_ + 0);                        \
+    P##b1 = *reinterpret_cast<const double2*>(bn_ + 2);                        \
     if constexpr (EA == 8) {                                                   \
-      ra2 = *reinterpret_cast<const double2*>(an_ + 4);                        \
-      ra3 = *reinterpret_cast<const double2*>(an_ + 6);                        \
-      rb2 = *reinterpret_cast<const double2*>(bn_ + 4);                        \
-      rb3 = *reinterpret_cast<const double2*>(bn_ + 6);                        \
+      P##a2 = *reinterpret_cast<const double2*>(an_ + 4);                      \
+      P##a3 = *reinterpret_cast<const double2*>(an_ + 6);                      \
+      P##b2 = *reinterpret_cast<const double2*>(bn_ + 4);                      \
+      P##b3 = *reinterpret_cast<const double2*>(bn_ + 6);                      \
     }                                                                          \
   } while (0)
-#define TD_G_STORE(buf)                                                        \
+#define TD_G_STORE(P, buf)                                                     \
   do {                                                                         \
-    As[buf][a_k + 0][a_row] = ra0.x;                                           \
-    As[buf][a_k + 1][a_row] = ra0.y;                                           \
-    As[buf][a_k + 2][a_row] = ra1.x;                                           \
-    As[buf][a_k + 3][a_row] = ra1.y;                                           \
-    *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n + 0]) = rb0;                 \
-    *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n + 2]) = rb1;                 \
+    As[buf][a_k + 0][a_row] = P##a0.x;                                         \
+    As[buf][a_k + 1][a_row] = P##a0.y;                                         \
+    As[buf][a_k + 2][a_row] = P##a1.x;                                         \
+    As[buf][a_k + 3][a_row] = P##a1.y;                                         \
+    *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n + 0]) = P##b0;               \
+    *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n + 2]) = P##b1;               \
     if constexpr (EA == 8) {                                                   \
-      As[buf][a_k + 4][a_row] = ra2.x;                                         \
-      As[buf][a_k + 5][a_row] = ra2.y;                                         \
-      As[buf][a_k + 6][a_row] = ra3.x;                                         \
-      As[buf][a_k + 7][a_row] = ra3.y;                                         \
-      *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n + 4]) = rb2;               \
-      *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n + 6]) = rb3;               \
+      As[buf][a_k + 4][a_row] = P##a2.x;                                       \
+      As[buf][a_k + 5][a_row] = P##a2.y;                                       \
+      As[buf][a_k + 6][a_row] = P##a3.x;                                       \
+      As[buf][a_k + 7][a_row] = P##a3.y;                                       \
+      *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n + 4]) = P##b2;             \
+      *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n + 6]) = P##b3;             \
+    }                                                                          \
+  } while (0)
+#define TD_G_COMPUTE(cur)                                                      \
+  do {                                                                         \
+    _Pragma("unroll") for (int kk = 0; kk < BK; kk += 4) {                     \
+      const int kl = kk + lk;                                                  \
+      double a[FR], b[FR];                                                     \
+      _Pragma("unroll") for (int i = 0; i < FR; ++i)                           \
+          a[i] = As[cur][kl][wm * (BT / 2) + i * 16 + l16];                    \
+      _Pragma("unroll") for (int j = 0; j < FR; ++j)                           \
+          b[j] = Bs[cur][kl][wn * (BT / 2) + j * 16 + l16];                    \
+      _Pragma("unroll") for (int i = 0; i < FR; ++i)                           \
+          _Pragma("unroll") for (int j = 0; j < FR; ++j) acc[i][j] =           \
+              __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0); \
     }                                                                          \
   } while (0)
 
   const int nk = Kp / BK;
-  TD_G_LOAD(0);
-  TD_G_STORE(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    const bool more = kt + 1 < nk;
-    if (more) TD_G_LOAD(kt + 1);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      const int kl = kk + lk;
-      double a[FR], b[FR];
-#pragma unroll
-      for (int i = 0; i < FR; ++i) a[i] = As[cur][kl][wm * (BT / 2) + i * 16 + l16];
-#pragma unroll
-      for (int j = 0; j < FR; ++j) b[j] = Bs[cur][kl][wn * (BT / 2) + j * 16 + l16];
-#pragma unroll
-      for (int i = 0; i < FR; ++i)
-#pragma unroll
-        for (int j = 0; j < FR; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-    if (more) TD_G_STORE(cur ^ 1);
+  if constexpr (BT == 64) {
+    const int last = nk - 1;
+    TD_G_LOAD(p, 0);
+    TD_G_LOAD(q, 1 < last ? 1 : last);
+    TD_G_STORE(p, 0);
+    TD_G_LOAD(p, 2 < last ? 2 : last);
     __syncthreads();
+    // Pairs of stages: LDS buffer 0 holds even tiles, buffer 1 odd ones; set
+    // q carries tile kt + 1, set p tile kt + 2 when a pair starts.
+    for (int kt = 0; kt < nk; kt += 2) {
+      TD_G_COMPUTE(0);
+      TD_G_STORE(q, 1);
+      __syncthreads();
+      TD_G_LOAD(q, kt + 3 < last ? kt + 3 : last);
+      if (kt + 1 >= nk) break;
+      TD_G_COMPUTE(1);
+      TD_G_STORE(p, 0);
+      __syncthreads();
+      TD_G_LOAD(p, kt + 4 < last ? kt + 4 : last);
+    }
+  } else {
+    // 128-wide tiles: one set, one stage ahead (the 16 accumulators leave no
+    // room for a second set at two workgroups per CU).
+    TD_G_LOAD(p, 0);
+    TD_G_STORE(p, 0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int cur = kt & 1;
+      const bool more = kt + 1 < nk;
+      if (more) TD_G_LOAD(p, kt + 1);
+      TD_G_COMPUTE(cur);
+      if (more) TD_G_STORE(p, cur ^ 1);
+      __syncthreads();
+    }
   }
 #undef TD_G_LOAD
 #undef TD_G_STORE
+#undef TD_G_COMPUTE
 
 #pragma unroll
   for (int i = 0; i < FR; ++i)

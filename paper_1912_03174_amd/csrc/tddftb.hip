@@ -748,6 +748,7 @@ td::ModelArgs model_args(td_ctx* c) {
   m.species = c->species;
   m.norb = c->norb;
   m.orb_off = c->orb_off;
+  m.atom_of = c->atom_of;
   m.sk_s = c->sk_s;
   m.sk_h = c->sk_h;
   m.scale_s = c->scale_s;
@@ -755,6 +756,7 @@ td::ModelArgs model_args(td_ctx* c) {
   m.onsite = c->onsite;
   m.na = c->na;
   m.nsp = c->nsp;
+  m.n = c->n;
   m.decay = c->decay;
   m.fd_step = std::pow(2.220446049250313e-16, 0.25);   // eps^(1/4) (Sec. 2.3, Eq. 20)
   return m;
