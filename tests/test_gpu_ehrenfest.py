@@ -80,6 +80,41 @@ def test_trajectory_matches_oracle():
     e.close()
 
 
+def test_spectrum_of_rho_s_conserved_on_a_prescribed_path():
+    """Straight-line nuclear paths with unequal velocities (masses 10^12
+    times larger): the GPU run follows the oracle and, like it, keeps the
+    spectrum of rho S (Sec. 2.1, Eq. 14: D + D^dagger = dS/dt) to the
+    leapfrog's second order."""
+    T = _T()
+    s = W.benzene()
+    m = W.two_centre_model(s)
+    heavy = dict(m, mass=m["mass"] * 1e12)
+    say("ehrenfest prescribed path benzene")
+    gs = O.ground_state(s, tol=1e-13)
+    Sinv = O.inverse_overlap(s.S)
+    vel = np.random.default_rng(3).standard_normal((s.n_atoms, 3)) * 0.006
+    n, dt = 100, 0.1
+    e = T.Ehrenfest(s, heavy, velocities=vel, dt=dt, rho0=gs.rho)
+    e.kick(5e-2, (1.0, 0.4, 0.0))
+    e.step(n)
+    pos, _ = e.nuclei()
+    rho = e.rho()[0]
+    rk = O.kick(gs.rho, s.S, Sinv, s.positions, s.orb_offset, 5e-2, (1.0, 0.4, 0.0))
+    ref = OE.propagate(s, heavy, rk, vel, n, dt)
+    assert np.abs(pos - ref.positions).max() < 1e-10
+    assert np.abs(rho - ref.rho).max() < 1e-10
+    S_end, _ = OE.model_matrices(m, pos)
+
+    def spec(r, S):
+        L = np.linalg.cholesky(S)
+        return np.linalg.eigvalsh(L.T @ r @ L)
+
+    dev = np.abs(spec(rho, S_end) - spec(rk, s.S)).max()
+    say(f"spectrum deviation {dev:.3e}")
+    assert dev < 2e-3
+    e.close()
+
+
 def test_energy_conserved_on_gpu():
     T = _T()
     s = W.flake_c24h16()

@@ -137,3 +137,70 @@ def test_nac_sums_to_overlap_derivative(benzene):
     assert np.abs(np.diag(D)).max() == 0.0
     Du = OE.nac(GS, np.tile([0.02, -0.01, 0.005], (s.n_atoms, 1)), atom_of)
     assert np.abs(Du + Du.T).max() < 1e-9 * np.abs(Du).max()
+
+
+def test_nac_moves_the_column_orbital(benzene):
+    """D_uv = <phi_u | d/dt phi_v> (Sec. 2.1, Eq. 14): the derivative of S_uv
+    when only the atom of v moves along its velocity. This fixes the index
+    convention (the transpose also satisfies D + D^T = dS/dt and conserves
+    the energy, so only a direct check tells them apart)."""
+    s, m = benzene
+    GS, _ = OE.fd_gradients(m, s.positions)
+    atom_of, _ = OE.orbital_types(m)
+    vel = np.random.default_rng(11).standard_normal((s.n_atoms, 3)) * 0.01
+    D = OE.nac(GS, vel, atom_of)
+    h = 1e-4
+    worst = 0.0
+    for u, v in [(0, 5), (5, 0), (3, 17), (17, 3), (1, 9), (20, 2)]:
+        b = atom_of[v]
+        if atom_of[u] == b:
+            continue
+        p = s.positions.copy()
+        p[b] += h * vel[b]
+        Sp, _ = OE.model_matrices(m, p)
+        p[b] -= 2 * h * vel[b]
+        Sm, _ = OE.model_matrices(m, p)
+        fd = (Sp[u, v] - Sm[u, v]) / (2 * h)
+        worst = max(worst, abs(D[u, v] - fd) / np.abs(D).max())
+        assert abs(D[v, u] - D[u, v]) > 1e-6 * np.abs(D).max()   # the pair is not symmetric
+    assert worst < 1e-8
+
+
+def _rho_s_spectrum(rho, S):
+    L = np.linalg.cholesky(S)
+    return np.linalg.eigvalsh(L.T @ rho @ L)
+
+
+def test_spectrum_of_rho_s_conserved_along_any_path(benzene):
+    """With D + D^dagger = dS/dt the exact motion is d(rho S)/dt = [G, rho S]
+    for G = -S^-1 (iH + D): the spectrum of rho S is conserved along any
+    nuclear path (uniform translation, the case of Sec. 2.1 remark b,
+    included). Leapfrog keeps it to second order in dt. The nuclei follow
+    straight lines with unequal velocities (masses 10^12 times larger);
+    dropping D (planted in the oracle) leaves an error that does not fall
+    with dt."""
+    s, m = benzene
+    heavy = dict(m, mass=m["mass"] * 1e12)
+    gs = O.ground_state(s, tol=1e-13)
+    Sinv = O.inverse_overlap(s.S)
+    rho = O.kick(gs.rho, s.S, Sinv, s.positions, s.orb_offset, 5e-2, (1.0, 0.4, 0.0))
+    lam0 = _rho_s_spectrum(rho, s.S)
+    vel = np.random.default_rng(3).standard_normal((s.n_atoms, 3)) * 0.006
+
+    def deviation(dt):
+        n = int(round(10.0 / dt))
+        tr = OE.propagate(s, heavy, rho, vel, n, dt)
+        S_end, _ = OE.model_matrices(m, tr.positions)
+        assert np.abs(tr.positions - s.positions).max() > 0.1   # the atoms moved
+        return np.abs(_rho_s_spectrum(tr.rho, S_end) - lam0).max()
+
+    dev = [deviation(dt) for dt in (0.2, 0.1, 0.05)]
+    assert dev[0] / dev[1] > 3.0 and dev[1] / dev[2] > 3.0
+    assert dev[2] < 5e-4
+    good = OE.nac
+    try:
+        OE.nac = lambda GS, v, a: 0.0 * good(GS, v, a)
+        dropped = [deviation(dt) for dt in (0.1, 0.05)]
+    finally:
+        OE.nac = good
+    assert dropped[1] > 0.5 * dropped[0] and dropped[1] > 20 * dev[2]
