@@ -82,6 +82,9 @@ def parse():
                     help="instead of the main line: FP64 steps/s of the N_orb=4096 strip with the "
                          "DFTB+U (FLL) correction on the carbon p shells, against the same steps "
                          "without it (--steps, --warmup)")
+    ap.add_argument("--small", action="store_true",
+                    help="the 112-orbital flake workload (500 steps, kick): solo context "
+                         "against a one-member batch replayed from HIP graphs")
     ap.add_argument("--validate", type=int, default=0,
                     help="instead of timing: propagate this many steps in FP64 and in "
                          "split-bf16 (--slices) from the same ground state and print the "
@@ -450,6 +453,51 @@ def batched_measure(count, steps, warmup, flags=0):
     return out
 
 
+def small(args):
+    """The 112-orbital flake (FP64, kick 0.001 au along x, dt 0.2 au): one
+    solo context against a one-member batch (the same trajectory bit for
+    bit) whose steps replay HIP graphs. At this size a step is a handful of
+    launches of a few microseconds, so launch overhead decides the rate.
+    Both run the same sequence: kick, warm-up steps (the batch captures its
+    graphs there), a second kick, then the timed steps."""
+    import workloads as W
+    from paper_1912_03174_amd import tddftb as T
+
+    w = W.workload(1)
+    s = w.system
+    e0, axis = w.kick
+    n = args.steps if args.steps != 200 else w.n_steps
+    warm = max(args.warmup, 1)
+    p = T.Propagator(s)
+    rho0 = p.rho()[0]
+    p.kick(e0, axis)
+    p.step(warm)
+    p.kick(e0, axis)
+    t0 = time.perf_counter()
+    mu_solo = p.step(n)
+    solo_s = time.perf_counter() - t0
+    p.close()
+    b = T.Batch([s], rho0s=[rho0])
+    b.kick(np.array([e0]), np.array([axis]))
+    b.step(warm)
+    b.kick(np.array([e0]), np.array([axis]))
+    t0 = time.perf_counter()
+    b.step(n)
+    batch_s = time.perf_counter() - t0
+    mu_batch = b.dipoles(0, n)
+    b.close()
+    print(json.dumps({
+        "metric": "density-matrix steps/s, 112-orbital flake (FP64)", "value": n / solo_s,
+        "unit": "steps/s", "n_gpus": 1, "steps": n, "warmup": warm,
+        "ms_per_step": 1e3 * solo_s / n, "higher_is_better": True, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_orb": s.n_orb, "path": "solo context"},
+        "trajectory_fs_per_s": n / solo_s * w.dt / W.FS,
+        "graph_replay_steps_per_s": n / batch_s, "graph_speedup": solo_s / batch_s,
+        "dipoles_bitwise_equal": bool(np.array_equal(mu_solo, mu_batch)),
+    }), flush=True)
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -478,6 +526,9 @@ def main():
         return
     if args.plus_u:
         plus_u(args)
+        return
+    if args.small:
+        small(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
