@@ -58,7 +58,7 @@ typedef enum {
   TD_ENOTPOSDEF = -4,   /* S is not positive definite (inverse diverged)   */
   TD_ESCF = -5,         /* ground state: SCC or purification not converged */
   TD_EUNSTABLE = -6,    /* non-finite values after a step                  */
-  TD_ENOTSUP = -7,      /* feature not available in this build             */
+  TD_ENOTSUP = -7,      /* feature not available in this library           */
   TD_ESTATE = -8        /* call not valid in the context's current state   */
 } td_status;
 
