@@ -371,9 +371,11 @@ def ehrenfest(args):
     field = w.field(0, args.warmup + args.steps)
     if args.warmup:
         e.step(args.warmup, field[:args.warmup])
+    upd0 = e.info()["inverse_updates"]
     t0 = time.perf_counter()
     e.step(args.steps, field[args.warmup:])
     el = time.perf_counter() - t0
+    info = e.info()
     ee, ek = e.energy_series(args.steps)
     e.close()
     n = s.n_orb
@@ -386,6 +388,8 @@ def ehrenfest(args):
         "product_tflops": 12.0 * n ** 3 * args.steps / el / 1e12,
         "init_s": init_s, "e_kin_start": float(ek[0]), "e_kin_end": float(ek[-1]),
         "e_total_change": float((ee[-1] + ek[-1]) - (ee[0] + ek[0])),
+        "inverse_updates_per_step": (info["inverse_updates"] - upd0) / args.steps,
+        "inverse_residual_last": info["inverse_residual"],
     }), flush=True)
 
 

@@ -147,6 +147,8 @@ typedef struct {
   int64_t step;                       /* index of the current rho            */
   int32_t has_prev;                   /* 0: next step is an Euler start      */
   int32_t precision;
+  int64_t inverse_updates;            /* Newton-Schulz updates of S^-1 since creation
+                                         (moving nuclei: along the trajectory) */
 } td_info;
 
 /* Kernel classes timed when td_options.profile = 1. In split-bf16

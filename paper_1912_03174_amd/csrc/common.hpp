@@ -207,7 +207,10 @@ hipError_t assemble_h_plus_u(hipStream_t s, const double* H0, const double* S, c
                              const int* sh_of, const int* sh_off, const double* V, double* H,
                              int np);
 // y = 2 x - y over len elements
-hipError_t extrapolate(hipStream_t s, const double* x, double* y, size_t len);
+// Extrapolation along a trajectory: out = 2 x0 - x1 (x2 null) or
+// 3 x0 - 3 x1 + x2; out may alias x1 or x2.
+hipError_t extrapolate(hipStream_t s, const double* x0, const double* x1, const double* x2,
+                       double* out, size_t len);
 // X = (emax I_n - T) / (emax - emin).
 hipError_t sp2_init(hipStream_t s, const double* T, double* X, int np, int n, double emax,
                     double emin);

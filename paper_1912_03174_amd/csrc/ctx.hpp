@@ -68,7 +68,8 @@ struct td_ctx {
   double *GS = nullptr, *GH = nullptr;   // 3 np x np each
   double *W = nullptr, *Dm = nullptr;    // np x np
   double *Sinv_prev = nullptr;           // np x np: S^-1 of the previous positions
-  bool sinv_prev_ok = false;
+  double *Sinv_prev2 = nullptr;          // np x np: S^-1 two positions back
+  int sinv_hist = 0;                     // inverses of earlier positions held (0..2)
   double *Z = nullptr;                   // np x 2np
   double *dgamma = nullptr;              // na x na x 3
   double *vel = nullptr, *F = nullptr;   // na x 3

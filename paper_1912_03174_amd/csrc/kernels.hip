@@ -239,9 +239,14 @@ __global__ void k_scaled_identity(double* X, int np, int n, double c) {
 }
 
 // y <- 2 x - y
-__global__ void k_extrapolate(const double* __restrict__ x, double* __restrict__ y, size_t len) {
+__global__ void k_extrapolate(const double* x0, const double* x1, const double* x2, double* out,
+                              size_t len) {
   const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx < len) y[idx] = 2.0 * x[idx] - y[idx];
+  if (idx >= len) return;
+  if (x2)
+    out[idx] = 3.0 * (x0[idx] - x1[idx]) + x2[idx];
+  else
+    out[idx] = 2.0 * x0[idx] - x1[idx];
 }
 
 __global__ void k_two_minus(double* T, int np, int n) {
@@ -655,9 +660,10 @@ hipError_t scaled_identity(hipStream_t s, double* X, int np, int n, double c) {
   return hipGetLastError();
 }
 
-hipError_t extrapolate(hipStream_t s, const double* x, double* y, size_t len) {
+hipError_t extrapolate(hipStream_t s, const double* x0, const double* x1, const double* x2,
+                       double* out, size_t len) {
   if (len == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_extrapolate, dim3(blocks_for(len)), dim3(256), 0, s, x, y, len);
+  hipLaunchKernelGGL(k_extrapolate, dim3(blocks_for(len)), dim3(256), 0, s, x0, x1, x2, out, len);
   return hipGetLastError();
 }
 

@@ -67,7 +67,7 @@ void free_all(td_ctx* c) {
     *b = nullptr;
   }
   double** ebufs[] = {&c->sk_s, &c->sk_h, &c->scale_s, &c->scale_h, &c->onsite, &c->mass,
-                      &c->GS, &c->GH, &c->W, &c->Dm, &c->Sinv_prev, &c->Z, &c->dgamma,
+                      &c->GS, &c->GH, &c->W, &c->Dm, &c->Sinv_prev, &c->Sinv_prev2, &c->Z, &c->dgamma,
                       &c->vel, &c->F,
                       &c->e_kin, &c->e_el, &c->sh_u, &c->sh_n, &c->sh_v, &c->sh_e,
                       &c->sh_nref,
@@ -139,14 +139,24 @@ void refresh(td_ctx* c) {
 void inverse_overlap(td_ctx* c, bool warm = false) {
   const int n = c->n, np = c->np;
   if (warm && c->Sinv_prev) {
-    if (c->sinv_prev_ok) {
-      HIPCHK(c, td::extrapolate(c->stream, c->Sinv, c->Sinv_prev, (size_t)np * np));
-      std::swap(c->Sinv, c->Sinv_prev);     // Sinv = 2 X_n - X_{n-1}, Sinv_prev = X_n
-    } else {
-      HIPCHK(c, hipMemcpyAsync(c->Sinv_prev, c->Sinv, sizeof(double) * np * (size_t)np,
+    // Start from the inverses at earlier positions of the trajectory: the
+    // quadratic extrapolation 3 X_n - 3 X_{n-1} + X_{n-2} (residual third
+    // order in the step), linear 2 X_n - X_{n-1} while only two are known,
+    // X_n itself at the first.
+    const size_t len = (size_t)np * np;
+    if (c->sinv_hist == 0) {
+      HIPCHK(c, hipMemcpyAsync(c->Sinv_prev, c->Sinv, sizeof(double) * len,
                                hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      HIPCHK(c, td::extrapolate(c->stream, c->Sinv, c->Sinv_prev,
+                                c->sinv_hist >= 2 ? c->Sinv_prev2 : nullptr, c->Sinv_prev2,
+                                len));
+      double* start = c->Sinv_prev2;         // X_{n-2} is overwritten by the start
+      c->Sinv_prev2 = c->Sinv_prev;
+      c->Sinv_prev = c->Sinv;
+      c->Sinv = start;
     }
-    c->sinv_prev_ok = true;
+    c->sinv_hist = std::min(c->sinv_hist + 1, 2);
   }
   if (!warm) {
     HIPCHK(c, td::gershgorin(c->stream, c->S, np, n, c->work1, c->work2, c->scal + SC_BOUNDS));
@@ -169,6 +179,7 @@ void inverse_overlap(td_ctx* c, bool warm = false) {
     HIPCHK(c, td::two_minus(c->stream, c->A, np, n));                   // 2 - S X
     gemm(c, 0, np, np, np, 1.0, c->Sinv, np, c->A, np, c->H, np);       // X (2 - S X)
     std::swap(c->Sinv, c->H);
+    c->info.inverse_updates += 1;
     // The residual I - S X squares with each update: from a warm start below
     // 1e-8 the updated inverse is at the rounding floor; stop without a check.
     if (warm && res < 1e-8) break;
@@ -1153,11 +1164,13 @@ void create_ehr_impl(td_ctx* c, const td_system* s, const td_model* m, const dou
   dalloc(c, &c->W, m2);
   dalloc(c, &c->Dm, m2);
   dalloc(c, &c->Sinv_prev, m2);
-  c->sinv_prev_ok = false;
+  dalloc(c, &c->Sinv_prev2, m2);
+  c->sinv_hist = 0;
   dalloc(c, &c->Z, 2 * m2);
   c->ehr = true;
   c->vel_half = false;
   rebuild_model(c, true);
+  c->sinv_hist = 0;   // that refinement is at the starting positions: no trajectory yet
   refresh(c);
 }
 

@@ -65,7 +65,7 @@ class TdInfo(ctypes.Structure):
                 ("purification_error", ctypes.c_double),
                 ("spectrum_lo", ctypes.c_double), ("spectrum_hi", ctypes.c_double),
                 ("step", ctypes.c_int64), ("has_prev", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("inverse_updates", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
