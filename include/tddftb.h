@@ -124,7 +124,7 @@ typedef struct {
 
 typedef struct {
   int32_t precision;           /* td_precision                                  */
-  int32_t n_slices;            /* split-bf16 slices per operand (3..6)          */
+  int32_t n_slices;            /* split-bf16 slices per operand (3..5)          */
   double dt;                   /* time step, au (> 0)                           */
   double scc_tol;              /* ground state: max |dq_out - dq_in| to stop    */
   int32_t scc_maxiter;         /* ground state: SCC cycle limit                 */
