@@ -14,6 +14,8 @@
 //    is remapped so each XCD owns a contiguous range of tiles, ordered in
 //    groups of 8 tile rows, so concurrently running tiles on one XCD share
 //    A and B panels in that XCD's L2.
+#include <atomic>
+
 #include "common.hpp"
 
 namespace td {
@@ -360,6 +362,24 @@ hipError_t dgemm_grouped(hipStream_t s, int tile, const GemmProblem* probs, int 
   return hipGetLastError();
 }
 
+namespace {
+// Compute units of the current device (queried once per device; racing
+// first queries store the same value).
+int cu_count() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int cu = cache[dev].load(std::memory_order_relaxed);
+  if (cu == 0) {
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cu <= 0)
+      cu = 256;
+    cache[dev].store(cu, std::memory_order_relaxed);
+  }
+  return cu;
+}
+}  // namespace
+
 hipError_t dgemm(hipStream_t s, int tag, int m, int n, int k, double alpha, const double* A,
                  int lda, const double* B, int ldb, double beta, const double* Cin, int ldcin,
                  double* C, int ldc) {
@@ -367,8 +387,17 @@ hipError_t dgemm(hipStream_t s, int tag, int m, int n, int k, double alpha, cons
   if (lda % 2 || ldb % 2 || lda < k || ldb < n || ldc < n) return hipErrorInvalidValue;
   if (beta != 0.0 && (Cin == nullptr || ldcin < n)) return hipErrorInvalidValue;
   const int tm = m / BM, tn = n / BN;
-  if (tm * tn < 512 && alpha == 1.0 && beta == 0.0) {
-    // too few 128-wide tiles for 256 CUs: 64-wide tiles, same sums in the same order
+  // 128-wide tiles run two per CU; they pay only when their last round of
+  // 2 x (CU count) workgroups is nearly full (at n = 2944, 529 tiles make a
+  // second round with 17 tiles in it and the product takes 17% longer than
+  // with 64-wide tiles, which fill the CUs more evenly). Otherwise 64-wide
+  // tiles: the same sums in the same order, so the result is bit for bit
+  // the same.
+  const int slots = 2 * cu_count();
+  const int t128 = tm * tn;
+  const int rounds = (t128 + slots - 1) / slots;
+  const bool full_rounds = 10 * (long long)t128 >= 9LL * rounds * slots;
+  if (!full_rounds && alpha == 1.0 && beta == 0.0) {
     GemmProblem pr{};
     pr.A = A;
     pr.B = B;
