@@ -573,7 +573,7 @@ def main():
         v["roofline"]["traffic"] = t
         v["hbm_GBps"] = None if t is None else t / (v["roofline"]["avg_launch_ms"] * 1e-3) / 1e9
     roof = dict(r["roofline"])
-    dtype = "f64" if best == "fp64" else f"bf16 (split x{args.slices}, fp32 accumulate, f64 combine)"
+    dtype = "f64" if best == "fp64" else "bf16"
     out = {
         "metric": "density-matrix steps/s at N_orb=4096 (FP64 vs split-BF16 @1e-6 dipole err)",
         "value": r["steps_per_s"],
@@ -586,6 +586,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": dtype,
+        "arithmetic": ("float64 products" if best == "fp64" else
+                       f"bf16 slices (x{args.slices}) on the matrix cores, fp32 accumulation, "
+                       "float64 combination"),
         "data": "synthetic",
         "config": {"workload": "strip4096", "system": "C938H344 armchair strip (seeded)",
                    "n_orb": s.n_orb, "n_atoms": s.n_atoms, "dt_au": w.dt,
