@@ -120,8 +120,6 @@ hipError_t gamma_build(hipStream_t s, const double* pos, int na, double u, doubl
 // D = sum_k vel[atom(v)][k] GS[k] on the n x n block of the np x np D.
 hipError_t nac_build(hipStream_t s, const double* GS, const double* vel, const int* atom_of,
                      int n, int np, double* D);
-// Wide X += -i Z.
-hipError_t add_minus_i(hipStream_t s, double* X, const double* Z, int np);
 // Forces F [na x 3] (Ehrenfest, without velocity terms).
 hipError_t ehrenfest_forces(hipStream_t s, const double* rho, int ldr, const double* W,
                             const double* GS, const double* GH, const double* vorb,
@@ -168,13 +166,15 @@ hipError_t assemble_h(hipStream_t s, const double* H0, const double* S, const do
 // Transpose-pair passes over np x np tiles (np multiple of 32):
 //  leapfrog:   out = base + f * rhodot with rhodot = -i (X - X^+),
 //              X = Xre + i Xim:  Re rhodot = Xim + Xim^T,  Im rhodot = Xre^T - Xre;
-//              with xref (leading dimension ldr), Xre = xre + xref
+//              with xref (leading dimension ldr), Xre = xre + xref; with zre, zim
+//              (leading dimension ldz), X = (xre + i xim) - i (zre + i zim)
 //  herm:       out = (T + T^+) / 2
 //  sym:        out_re = (T + T^T) / 2 (real), out_im = 0 when given
 hipError_t pair_leapfrog(hipStream_t s, const double* xre, const double* xim, int ldx,
                          const double* bre, const double* bim, int ldb, double* ore,
                          double* oim, int ldo, int np, double f, const double* xref = nullptr,
-                         int ldr = 0);
+                         int ldr = 0, const double* zre = nullptr, const double* zim = nullptr,
+                         int ldz = 0);
 hipError_t pair_herm(hipStream_t s, const double* tre, const double* tim, int ldt,
                      double* ore, double* oim, int ldo, int np);
 hipError_t pair_sym(hipStream_t s, const double* t, int ldt, double* ore, double* oim,

@@ -137,17 +137,6 @@ __global__ void k_nac(const double* __restrict__ GS, const double* __restrict__ 
   D[e] = w[0] * GS[e] + w[1] * GS[nn + e] + w[2] * GS[2 * nn + e];
 }
 
-// Wide X (np x 2np) += -i Z: Re X += Im Z, Im X -= Re Z.
-__global__ void k_add_minus_i(double* __restrict__ X, const double* __restrict__ Z, int np) {
-  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (size_t)np * np) return;
-  const int r = (int)(idx / np), c = (int)(idx % np);
-  const size_t re = (size_t)r * 2 * np + c, im = re + np;
-  const double zr = Z[re], zi = Z[im];
-  X[re] += zi;
-  X[im] -= zr;
-}
-
 // One block per atom A:
 // F_A = 2 sum_{u in A, v} [Re rho_uv GH_uv + (1/2 Re rho_uv (v_u + v_v) - W_uv) GS_uv]
 //       - dq_A sum_B dgamma_AB dq_B - dq_A E.
@@ -241,11 +230,6 @@ hipError_t nac_build(hipStream_t s, const double* GS, const double* vel, const i
                      int np, double* D) {
   hipLaunchKernelGGL(k_nac, dim3(nblocks((size_t)n * n)), dim3(256), 0, s, GS, vel, atom_of, n, np,
                      D);
-  return hipGetLastError();
-}
-
-hipError_t add_minus_i(hipStream_t s, double* X, const double* Z, int np) {
-  hipLaunchKernelGGL(k_add_minus_i, dim3(nblocks((size_t)np * np)), dim3(256), 0, s, X, Z, np);
   return hipGetLastError();
 }
 

@@ -125,7 +125,8 @@ template <int MODE>
 __global__ __launch_bounds__(256) void k_pair(const double* xre, const double* xim, int ldx,
                                               const double* bre, const double* bim, int ldb,
                                               double* ore, double* oim, int ldo, double f,
-                                              const double* xref, int ldr) {
+                                              const double* xref, int ldr, const double* zre,
+                                              const double* zim, int ldz) {
   const int bi = blockIdx.y, bj = blockIdx.x;
   if (bi > bj) return;
   __shared__ double sre[2][TS][TLD];   // [0]: tile (bi,bj), [1]: tile (bj,bi)
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(256) void k_pair(const double* xre, const double* x
   const int tr = t >> 3, tc = (t & 7) * 4;
   const bool diag = (bi == bj);
   const int nt = diag ? 1 : 2;
-  double2 xr[2][2], xi[2][2], br[2][2], bm[2][2], xf[2][2];
+  double2 xr[2][2], xi[2][2], br[2][2], bm[2][2], xf[2][2], zr[2][2], zi[2][2];
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
     if (p < nt) {
@@ -150,6 +151,13 @@ __global__ __launch_bounds__(256) void k_pair(const double* xre, const double* x
       if (MODE != PAIR_SYM) {
         xi[p][0] = *reinterpret_cast<const double2*>(xim + g);
         xi[p][1] = *reinterpret_cast<const double2*>(xim + g + 2);
+      }
+      if (MODE == PAIR_LEAPFROG && zre) {
+        const size_t gz = (size_t)(ti * TS + tr) * ldz + tj * TS + tc;
+        zr[p][0] = *reinterpret_cast<const double2*>(zre + gz);
+        zr[p][1] = *reinterpret_cast<const double2*>(zre + gz + 2);
+        zi[p][0] = *reinterpret_cast<const double2*>(zim + gz);
+        zi[p][1] = *reinterpret_cast<const double2*>(zim + gz + 2);
       }
       if (MODE == PAIR_LEAPFROG) {
         const size_t gb = (size_t)(ti * TS + tr) * ldb + tj * TS + tc;
@@ -168,6 +176,12 @@ __global__ __launch_bounds__(256) void k_pair(const double* xre, const double* x
         if (MODE == PAIR_LEAPFROG && xref) {
           xr[p][h].x = xr[p][h].x + xf[p][h].x;
           xr[p][h].y = xr[p][h].y + xf[p][h].y;
+        }
+        if (MODE == PAIR_LEAPFROG && zre) {      // X - i Z
+          xr[p][h].x = xr[p][h].x + zi[p][h].x;
+          xr[p][h].y = xr[p][h].y + zi[p][h].y;
+          xi[p][h].x = xi[p][h].x - zr[p][h].x;
+          xi[p][h].y = xi[p][h].y - zr[p][h].y;
         }
         sre[p][tr][tc + 2 * h] = xr[p][h].x;
         sre[p][tr][tc + 2 * h + 1] = xr[p][h].y;
@@ -619,11 +633,13 @@ hipError_t assemble_h(hipStream_t s, const double* H0, const double* S, const do
 
 hipError_t pair_leapfrog(hipStream_t s, const double* xre, const double* xim, int ldx,
                          const double* bre, const double* bim, int ldb, double* ore, double* oim,
-                         int ldo, int np, double f, const double* xref, int ldr) {
+                         int ldo, int np, double f, const double* xref, int ldr,
+                         const double* zre, const double* zim, int ldz) {
   if (np % TS) return hipErrorInvalidValue;
+  if ((zre == nullptr) != (zim == nullptr)) return hipErrorInvalidValue;
   const dim3 grid(np / TS, np / TS);
   hipLaunchKernelGGL(k_pair<PAIR_LEAPFROG>, grid, dim3(256), 0, s, xre, xim, ldx, bre, bim, ldb,
-                     ore, oim, ldo, f, xref, ldr);
+                     ore, oim, ldo, f, xref, ldr, zre, zim, ldz);
   return hipGetLastError();
 }
 
@@ -633,7 +649,8 @@ hipError_t pair_herm(hipStream_t s, const double* tre, const double* tim, int ld
   const dim3 grid(np / TS, np / TS);
   hipLaunchKernelGGL(k_pair<PAIR_HERM>, grid, dim3(256), 0, s, tre, tim, ldt,
                      (const double*)nullptr, (const double*)nullptr, 0, ore, oim, ldo, 0.0,
-                     (const double*)nullptr, 0);
+                     (const double*)nullptr, 0, (const double*)nullptr, (const double*)nullptr,
+                     0);
   return hipGetLastError();
 }
 
@@ -643,7 +660,8 @@ hipError_t pair_sym(hipStream_t s, const double* t, int ldt, double* ore, double
   const dim3 grid(np / TS, np / TS);
   hipLaunchKernelGGL(k_pair<PAIR_SYM>, grid, dim3(256), 0, s, t, (const double*)nullptr, ldt,
                      (const double*)nullptr, (const double*)nullptr, 0, ore, oim, ldo, 0.0,
-                     (const double*)nullptr, 0);
+                     (const double*)nullptr, 0, (const double*)nullptr, (const double*)nullptr,
+                     0);
   return hipGetLastError();
 }
 

@@ -815,13 +815,15 @@ void ehr_step(td_ctx* c, int k, const double* E) {
   HIPCHK(c, td::nac_build(st, c->GS, c->vel, c->atom_of, c->n, np, c->Dm));
   gemm(c, 0, np, np, np, 1.0, c->Sinv, np, c->Dm, np, c->A, np);
   gemm(c, 0, np, 2 * np, np, 1.0, c->A, np, c->rho_cur, 2 * np, c->Z, 2 * np);
-  HIPCHK(c, td::add_minus_i(st, c->X, c->Z, np));
+  // the leapfrog pass stages X - i Z (the coupling term) as it reads X
   if (c->has_prev) {
     HIPCHK(c, td::pair_leapfrog(st, c->X, c->X + np, 2 * np, c->rho_prev, c->rho_prev + np,
-                                2 * np, c->rho_prev, c->rho_prev + np, 2 * np, np, 2.0 * dt));
+                                2 * np, c->rho_prev, c->rho_prev + np, 2 * np, np, 2.0 * dt,
+                                nullptr, 0, c->Z, c->Z + np, 2 * np));
   } else {
     HIPCHK(c, td::pair_leapfrog(st, c->X, c->X + np, 2 * np, c->rho_cur, c->rho_cur + np,
-                                2 * np, c->rho_prev, c->rho_prev + np, 2 * np, np, dt));
+                                2 * np, c->rho_prev, c->rho_prev + np, 2 * np, np, dt, nullptr, 0,
+                                c->Z, c->Z + np, 2 * np));
     c->has_prev = true;
   }
   std::swap(c->rho_cur, c->rho_prev);
