@@ -64,7 +64,14 @@ def test_trajectory_matches_oracle():
     field = W.sin2_pulse(np.arange(n) * 0.2, 0.01, 0.4, n * 0.2, (1.0, 0.5, 0.2))
     e = T.Ehrenfest(s, m, velocities=vel, rho0=gs.rho)
     e.kick(1e-3, (0.0, 1.0, 0.0))
+    upd0 = e.info()["inverse_updates"]
     mu = e.step(n, field)
+    # S^-1 at each new geometry: from the third-order start along the
+    # trajectory one Newton-Schulz update per step reaches the rounding floor
+    # (two when the start is further off; the first steps have less history)
+    upd = e.info()["inverse_updates"] - upd0
+    say(f"inverse updates {upd} over {n} steps")
+    assert n <= upd <= 2 * n
     ee, ek = e.energy_series(n)
     pos, _ = e.nuclei()
     rho = e.rho()[0]
