@@ -166,14 +166,17 @@ __global__ __launch_bounds__(256) void dgemm_nn(const double* __restrict__ A, in
 
 // Grouped form: the block id picks a problem (binary search over tile0)
 // and a tile inside it. BT = 128: the same waves, LDS staging and MFMA
-// sequence as dgemm_nn; BT = 64: four waves of 32 x 32 (2 x 2 MFMA blocks
-// each) for small matrices, where 128-wide tiles would mostly multiply
-// padding. Each output element sees the same MFMA sequence over k in both.
+// sequence as dgemm_nn (256 threads); BT = 64: eight waves of 32 x 16
+// (2 x 1 MFMA blocks each, 512 threads) for small matrices, where 128-wide
+// tiles would mostly multiply padding. Each output element sees the same
+// MFMA sequence over k in both.
 template <int BT>
 __device__ __forceinline__ void dgemm_tile_body(const GemmProblem* __restrict__ pp, int local);
+__device__ __forceinline__ void dgemm_tile64(const GemmProblem* __restrict__ pp, int local);
 
 template <int BT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BT == 64 ? 4 : 1)))
+__global__ __launch_bounds__(BT == 64 ? 512 : 256)
+__attribute__((amdgpu_waves_per_eu(BT == 64 ? 6 : 1)))
 void dgemm_grouped_k(const GemmProblem* __restrict__ probs, int nprob, int ntiles) {
   // XCD-aware order over the launch's tiles (a problem's tiles stay together).
   const int w = blockIdx.x;
@@ -185,25 +188,119 @@ void dgemm_grouped_k(const GemmProblem* __restrict__ probs, int nprob, int ntile
     const int mid = (lo + hi + 1) >> 1;
     if (probs[mid].tile0 <= lin) lo = mid; else hi = mid - 1;
   }
-  dgemm_tile_body<BT>(probs + lo, lin - probs[lo].tile0);
+  if constexpr (BT == 64)
+    dgemm_tile64(probs + lo, lin - probs[lo].tile0);
+  else
+    dgemm_tile_body<BT>(probs + lo, lin - probs[lo].tile0);
 }
 
 // One problem passed by value (no device table): the 64-tile form for
-// products with too few 128 x 128 tiles to fill the chip.
+// products whose 128 x 128 tiles would fill the chip's rounds badly.
 template <int BT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BT == 64 ? 4 : 1)))
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6)))
 void dgemm_single_k(GemmProblem pr) {
+  static_assert(BT == 64, "single-problem launches use the 64-wide tile");
   const int ntiles = pr.tiles_m * pr.tiles_n;
   const int w = blockIdx.x;
   const int q = ntiles >> 3, r = ntiles & 7;
   const int xcd = w & 7, slot = w >> 3;
-  dgemm_tile_body<BT>(&pr, xcd * q + (xcd < r ? xcd : r) + slot);
+  dgemm_tile64(&pr, xcd * q + (xcd < r ? xcd : r) + slot);
+}
+
+// 64 x 64 tile over eight waves in 2 x 4, each 32 rows x 16 columns (two
+// 16 x 16 MFMA blocks sharing the B operand). Twice the waves of a 4-wave
+// layout, for latency hiding at the 2-3 workgroups per CU that products of
+// n ~ 1000-3000 give. K stages of 16 are loaded two stages ahead from two
+// register sets (one stage is 8 MFMAs per wave, shorter than the load
+// latency); prefetch indices are clamped to the last stage (a harmless
+// reload) so the loop body is straight-line.
+__device__ __forceinline__ void dgemm_tile64(const GemmProblem* __restrict__ pp, int local) {
+  constexpr int T = 64;
+  __shared__ double As[2][BK][T + PAD];
+  __shared__ double Bs[2][BK][T + PAD];
+  const int tiles_m = pp->tiles_m, tiles_n = pp->tiles_n;
+  const int lda = pp->lda, ldb = pp->ldb, ldc = pp->ldc, Kp = pp->K;
+  const double* __restrict__ Ap = pp->A;
+  const double* __restrict__ Bp = pp->B;
+  double* Cp = pp->C;
+  const int group = GROUP_M * tiles_n;
+  const int g = local / group;
+  const int first_m = g * GROUP_M;
+  const int gsz = (tiles_m - first_m) < GROUP_M ? (tiles_m - first_m) : GROUP_M;
+  const int in_g = local - g * group;
+  const int m0 = (first_m + in_g % gsz) * T, n0 = (in_g / gsz) * T;
+
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 2, wn = wave & 3;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int a_row = t >> 3, a_k = (t & 7) * 2;      // A: 64 rows x 16 k, one double2 a thread
+  const int b_k = t >> 5, b_n = (t & 31) * 2;       // B: 16 k x 64 columns, one double2 a thread
+  const double* Ag = Ap + (size_t)(m0 + a_row) * lda + a_k;
+  const double* Bg = Bp + (size_t)b_k * ldb + n0 + b_n;
+
+  d4 acc0 = d4{0.0, 0.0, 0.0, 0.0}, acc1 = d4{0.0, 0.0, 0.0, 0.0};
+  double2 pa, pb, qa, qb;   // two staging sets (named, so they stay in VGPRs)
+#define TD_W_LOAD(P, kt)                                                       \
+  do {                                                                         \
+    P##a = *reinterpret_cast<const double2*>(Ag + (size_t)(kt) * BK);          \
+    P##b = *reinterpret_cast<const double2*>(Bg + (size_t)(kt) * BK * ldb);    \
+  } while (0)
+#define TD_W_STORE(P, buf)                                                     \
+  do {                                                                         \
+    As[buf][a_k][a_row] = P##a.x;                                              \
+    As[buf][a_k + 1][a_row] = P##a.y;                                          \
+    *reinterpret_cast<double2*>(&Bs[buf][b_k][b_n]) = P##b;                    \
+  } while (0)
+#define TD_W_COMPUTE(cur)                                                      \
+  do {                                                                         \
+    _Pragma("unroll") for (int kk = 0; kk < BK; kk += 4) {                     \
+      const int kl = kk + lk;                                                  \
+      const double a0 = As[cur][kl][wm * 32 + l16];                            \
+      const double a1 = As[cur][kl][wm * 32 + 16 + l16];                       \
+      const double b0 = Bs[cur][kl][wn * 16 + l16];                            \
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);      \
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc1, 0, 0, 0);      \
+    }                                                                          \
+  } while (0)
+  const int nk = Kp / BK, last = nk - 1;
+  TD_W_LOAD(p, 0);
+  TD_W_LOAD(q, 1 < last ? 1 : last);
+  TD_W_STORE(p, 0);
+  TD_W_LOAD(p, 2 < last ? 2 : last);
+  __syncthreads();
+  // Pairs of stages: LDS buffer 0 holds even stages, buffer 1 odd ones; set
+  // q carries stage kt + 1, set p stage kt + 2 when a pair starts.
+  for (int kt = 0; kt < nk; kt += 2) {
+    TD_W_COMPUTE(0);
+    TD_W_STORE(q, 1);
+    __syncthreads();
+    TD_W_LOAD(q, kt + 3 < last ? kt + 3 : last);
+    if (kt + 1 >= nk) break;
+    TD_W_COMPUTE(1);
+    TD_W_STORE(p, 0);
+    __syncthreads();
+    TD_W_LOAD(p, kt + 4 < last ? kt + 4 : last);
+  }
+#undef TD_W_LOAD
+#undef TD_W_STORE
+#undef TD_W_COMPUTE
+  // output layout of a 16 x 16 block: register rr of lane l holds row
+  // l / 16 + 4 rr, column l % 16
+  const int col = n0 + wn * 16 + l16;
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int row = m0 + wm * 32 + lk + 4 * rr;
+    Cp[(size_t)row * ldc + col] = acc0[rr];
+    Cp[(size_t)(row + 16) * ldc + col] = acc1[rr];
+  }
 }
 
 template <int BT>
 __device__ __forceinline__ void dgemm_tile_body(const GemmProblem* __restrict__ pp, int local) {
   constexpr int FR = BT / 32;                 // 16 x 16 blocks per wave dimension
-  constexpr int EA = BT * BK / 256;           // A (and B) elements loaded per thread: 8 or 4
+  static_assert(BT == 128, "the 64-wide tile has its own body (dgemm_tile64)");
+  constexpr int EA = BT * BK / 256;           // A (and B) elements loaded per thread: 8
   constexpr int EB = EA;
   constexpr int LD = BT + PAD;
   __shared__ double As[2][BK][LD];
@@ -239,15 +336,9 @@ __device__ __forceinline__ void dgemm_tile_body(const GemmProblem* __restrict__ 
 #pragma unroll
     for (int j = 0; j < FR; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  // Staging registers (named, so they stay in VGPRs; x2/x3 unused for
-  // BT = 64). 64-wide tiles use two sets: tile t of K is loaded into set
-  // t & 1 two compute stages before it is stored to LDS, so a global load has
-  // two stages of matrix-core work to arrive (one stage of a 64-wide tile is
-  // short). Prefetch indices are clamped to the last tile (a harmless
-  // reload) so the loop body is straight-line and each store waits only for
-  // the older set.
+  // staging registers (named, so they stay in VGPRs): the next stage's
+  // global loads are in flight while the matrix cores work on this one
   double2 pa0, pa1, pa2, pa3, pb0, pb1, pb2, pb3;
-  double2 qa0, qa1, qa2, qa3, qb0, qb1, qb2, qb3;
 #define TD_G_LOAD(P, kt)                                                       \
   do {                                                                         \
     const double* an_ = Ag + (size_t)(kt) * BK;                                \
@@ -296,40 +387,16 @@ __device__ __forceinline__ void dgemm_tile_body(const GemmProblem* __restrict__ 
   } while (0)
 
   const int nk = Kp / BK;
-  if constexpr (BT == 64) {
-    const int last = nk - 1;
-    TD_G_LOAD(p, 0);
-    TD_G_LOAD(q, 1 < last ? 1 : last);
-    TD_G_STORE(p, 0);
-    TD_G_LOAD(p, 2 < last ? 2 : last);
+  TD_G_LOAD(p, 0);
+  TD_G_STORE(p, 0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) TD_G_LOAD(p, kt + 1);
+    TD_G_COMPUTE(cur);
+    if (more) TD_G_STORE(p, cur ^ 1);
     __syncthreads();
-    // Pairs of stages: LDS buffer 0 holds even tiles, buffer 1 odd ones; set
-    // q carries tile kt + 1, set p tile kt + 2 when a pair starts.
-    for (int kt = 0; kt < nk; kt += 2) {
-      TD_G_COMPUTE(0);
-      TD_G_STORE(q, 1);
-      __syncthreads();
-      TD_G_LOAD(q, kt + 3 < last ? kt + 3 : last);
-      if (kt + 1 >= nk) break;
-      TD_G_COMPUTE(1);
-      TD_G_STORE(p, 0);
-      __syncthreads();
-      TD_G_LOAD(p, kt + 4 < last ? kt + 4 : last);
-    }
-  } else {
-    // 128-wide tiles: one set, one stage ahead (the 16 accumulators leave no
-    // room for a second set at two workgroups per CU).
-    TD_G_LOAD(p, 0);
-    TD_G_STORE(p, 0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-      const int cur = kt & 1;
-      const bool more = kt + 1 < nk;
-      if (more) TD_G_LOAD(p, kt + 1);
-      TD_G_COMPUTE(cur);
-      if (more) TD_G_STORE(p, cur ^ 1);
-      __syncthreads();
-    }
   }
 #undef TD_G_LOAD
 #undef TD_G_STORE
@@ -356,7 +423,7 @@ hipError_t dgemm_grouped(hipStream_t s, int tile, const GemmProblem* probs, int 
   if (tile == 128)
     hipLaunchKernelGGL(dgemm_grouped_k<128>, dim3(ntiles), dim3(256), 0, s, probs, nprob, ntiles);
   else if (tile == 64)
-    hipLaunchKernelGGL(dgemm_grouped_k<64>, dim3(ntiles), dim3(256), 0, s, probs, nprob, ntiles);
+    hipLaunchKernelGGL(dgemm_grouped_k<64>, dim3(ntiles), dim3(512), 0, s, probs, nprob, ntiles);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -408,7 +475,7 @@ hipError_t dgemm(hipStream_t s, int tag, int m, int n, int k, double alpha, cons
     pr.K = k;
     pr.tiles_m = m / 64;
     pr.tiles_n = n / 64;
-    hipLaunchKernelGGL(dgemm_single_k<64>, dim3(pr.tiles_m * pr.tiles_n), dim3(256), 0, s, pr);
+    hipLaunchKernelGGL(dgemm_single_k<64>, dim3(pr.tiles_m * pr.tiles_n), dim3(512), 0, s, pr);
     return hipGetLastError();
   }
   const dim3 grid(tm * tn), block(256);
