@@ -196,3 +196,17 @@ def test_plus_u_arguments_rejected_before_device(T):
     with pytest.raises(T.TdError) as e:
         T.td_create_ehrenfest(b, W.two_centre_model(b), plus_u=_PU("psic", boff, bu))
     assert e.value.status == T.TD_ENOTSUP
+
+
+def test_missing_library_fails_loudly():
+    """Without the built library the binding raises; nothing falls back to
+    a CPU path (fresh interpreter, so no library is loaded yet)."""
+    import subprocess
+    import sys
+    code = ("from paper_1912_03174_amd import tddftb as T\n"
+            "T.load('/nonexistent/libtddftb.so')\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                       cwd=str(__import__('pathlib').Path(__file__).resolve().parents[1]),
+                       timeout=120)
+    assert r.returncode != 0
+    assert "FileNotFoundError" in r.stderr and "is not built" in r.stderr
