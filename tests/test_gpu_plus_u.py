@@ -139,3 +139,35 @@ def test_zero_u_is_bitwise_the_plain_path(flake, ground):
     assert np.array_equal(a.rho()[0], b.rho()[0])
     a.close()
     b.close()
+
+
+@pytest.fixture(scope="module")
+def strip648_fll():
+    """A 648-orbital strip with FLL corrections on 358 shells (many tiles of
+    every product), its corrected ground state and a 20-step kicked oracle run."""
+    s = W.small_strip(20, 10, seed=1)
+    pu = _pu(s, U.FLL)
+    g = U.ground_state(s, pu, tol=1e-12)
+    Sinv = O.inverse_overlap(s.S)
+    rk = O.kick(g.rho, s.S, Sinv, s.positions, s.orb_offset, 1e-3, (1.0, 0.0, 0.0))
+    rho, _, mus, _ = U.propagate(s, pu, rk, 20, 0.2, Sinv=Sinv)
+    return s, pu, g, rho, mus
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_multi_tile_corrected_run(strip648_fll, precision):
+    T = _T()
+    s, pu, g, rho, mus = strip648_fll
+    say(f"plus_u strip648 {precision}")
+    prec = T.TD_FP64 if precision == "fp64" else T.TD_SPLIT_BF16
+    p = T.Propagator(s, rho0=g.rho, plus_u=pu, precision=prec, n_slices=4)
+    p.kick(1e-3, (1.0, 0.0, 0.0))
+    mu = p.step(20)
+    err = np.abs(mu - mus).max() / np.abs(mus - mus[0]).max()
+    say(f"dipole relative error {err:.3e}")
+    if precision == "fp64":
+        assert err < 1e-10
+        assert np.abs(p.rho()[0] - rho).max() < 1e-12
+    else:
+        assert err < 1e-6
+    p.close()
