@@ -87,6 +87,32 @@ def test_trajectory_matches_oracle():
     e.close()
 
 
+def test_multi_tile_trajectory_matches_oracle():
+    """A 276-orbital strip (93 atoms, every product several tiles) with
+    thermal nuclei and a kick: dipoles, positions and rho against the oracle."""
+    T = _T()
+    s = W.small_strip(8, 4, seed=1)
+    m = W.two_centre_model(s)
+    say(f"ehrenfest trajectory strip n_orb={s.n_orb}")
+    gs = O.ground_state(s, tol=1e-13)
+    Sinv = O.inverse_overlap(s.S)
+    vel = W.thermal_velocities(s, 600.0, seed=3)
+    n = 30
+    e = T.Ehrenfest(s, m, velocities=vel, rho0=gs.rho)
+    e.kick(1e-3, (1.0, 0.0, 0.0))
+    mu = e.step(n)
+    pos, _ = e.nuclei()
+    rho = e.rho()[0]
+    rk = O.kick(gs.rho, s.S, Sinv, s.positions, s.orb_offset, 1e-3, (1.0, 0.0, 0.0))
+    ref = OE.propagate(s, m, rk, vel, n, 0.2)
+    d_err = np.abs(mu - ref.dipoles).max() / np.abs(ref.dipoles - ref.dipoles[0]).max()
+    say(f"dipole relative difference {d_err:.2e}")
+    assert d_err < 1e-8
+    assert np.abs(pos - ref.positions).max() < 1e-10
+    assert np.abs(rho - ref.rho).max() < 1e-10
+    e.close()
+
+
 def test_spectrum_of_rho_s_conserved_on_a_prescribed_path():
     """Straight-line nuclear paths with unequal velocities (masses 10^12
     times larger): the GPU run follows the oracle and, like it, keeps the
