@@ -24,6 +24,11 @@ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 // dimensions in elements; m, n multiples of kGemmTile, k multiple of 16.
 // `tag` only selects a separately named kernel instance (so profilers
 // separate the two products of a step): 0 generic, 1 S^-1 H, 2 A rho.
+// C (n x n) = A B for a product known to be symmetric in exact arithmetic:
+// the 64-wide tiles on and above the diagonal are computed, the ones below
+// are copied from their transposes. n a multiple of 64, k of 16.
+hipError_t dgemm_symmetric(hipStream_t s, int n, int k, const double* A, int lda,
+                           const double* B, int ldb, double* C, int ldc);
 hipError_t dgemm(hipStream_t s, int tag, int m, int n, int k, double alpha,
                  const double* A, int lda, const double* B, int ldb, double beta,
                  const double* Cin, int ldcin, double* C, int ldc);
@@ -37,7 +42,8 @@ struct GemmProblem {
   const double* B;
   double* C;
   int lda, ldb, ldc, K;
-  int tiles_m, tiles_n, tile0, pad_;
+  int tiles_m, tiles_n, tile0;
+  int upper;   // 1: only the tiles on or above the diagonal (square, symmetric C)
 };
 
 // All problems of `probs` (device array, nprob entries, ntiles tiles in

@@ -200,7 +200,7 @@ template <int BT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6)))
 void dgemm_single_k(GemmProblem pr) {
   static_assert(BT == 64, "single-problem launches use the 64-wide tile");
-  const int ntiles = pr.tiles_m * pr.tiles_n;
+  const int ntiles = pr.upper ? pr.tiles_n * (pr.tiles_n + 1) / 2 : pr.tiles_m * pr.tiles_n;
   const int w = blockIdx.x;
   const int q = ntiles >> 3, r = ntiles & 7;
   const int xcd = w & 7, slot = w >> 3;
@@ -223,12 +223,25 @@ __device__ __forceinline__ void dgemm_tile64(const GemmProblem* __restrict__ pp,
   const double* __restrict__ Ap = pp->A;
   const double* __restrict__ Bp = pp->B;
   double* Cp = pp->C;
-  const int group = GROUP_M * tiles_n;
-  const int g = local / group;
-  const int first_m = g * GROUP_M;
-  const int gsz = (tiles_m - first_m) < GROUP_M ? (tiles_m - first_m) : GROUP_M;
-  const int in_g = local - g * group;
-  const int m0 = (first_m + in_g % gsz) * T, n0 = (in_g / gsz) * T;
+  int m0, n0;
+  if (pp->upper) {
+    // the tiles with tile row <= tile column, row by row
+    int r = 0, rem = local;
+    while (rem >= tiles_n - r) {
+      rem -= tiles_n - r;
+      ++r;
+    }
+    m0 = r * T;
+    n0 = (r + rem) * T;
+  } else {
+    const int group = GROUP_M * tiles_n;
+    const int g = local / group;
+    const int first_m = g * GROUP_M;
+    const int gsz = (tiles_m - first_m) < GROUP_M ? (tiles_m - first_m) : GROUP_M;
+    const int in_g = local - g * group;
+    m0 = (first_m + in_g % gsz) * T;
+    n0 = (in_g / gsz) * T;
+  }
 
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -416,6 +429,46 @@ __device__ __forceinline__ void dgemm_tile_body(const GemmProblem* __restrict__ 
 }
 
 }  // namespace
+
+namespace {
+// Lower 64-wide tiles of a symmetric C from their transposes: 32 x 32
+// blocks (bi, bj) with bi > bj outside the diagonal 64-tiles, staged
+// through LDS so both the reads and the writes are row-contiguous.
+__global__ __launch_bounds__(256) void k_mirror_lower(double* C, int ldc) {
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bi <= bj || (bi >> 1) == (bj >> 1)) return;
+  __shared__ double t[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+#pragma unroll
+  for (int r = ty; r < 32; r += 8) t[r][tx] = C[(size_t)(bj * 32 + r) * ldc + bi * 32 + tx];
+  __syncthreads();
+#pragma unroll
+  for (int r = ty; r < 32; r += 8) C[(size_t)(bi * 32 + r) * ldc + bj * 32 + tx] = t[tx][r];
+}
+}  // namespace
+
+hipError_t dgemm_symmetric(hipStream_t s, int n, int k, const double* A, int lda,
+                           const double* B, int ldb, double* C, int ldc) {
+  if (n <= 0 || k <= 0 || n % 64 || k % BK) return hipErrorInvalidValue;
+  if (lda % 2 || ldb % 2 || lda < k || ldb < n || ldc < n) return hipErrorInvalidValue;
+  GemmProblem pr{};
+  pr.A = A;
+  pr.B = B;
+  pr.C = C;
+  pr.lda = lda;
+  pr.ldb = ldb;
+  pr.ldc = ldc;
+  pr.K = k;
+  pr.tiles_m = n / 64;
+  pr.tiles_n = n / 64;
+  pr.upper = 1;
+  const int t = n / 64;
+  hipLaunchKernelGGL(dgemm_single_k<64>, dim3(t * (t + 1) / 2), dim3(512), 0, s, pr);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mirror_lower, dim3(n / 32, n / 32), dim3(256), 0, s, C, ldc);
+  return hipGetLastError();
+}
 
 hipError_t dgemm_grouped(hipStream_t s, int tile, const GemmProblem* probs, int nprob,
                          int ntiles) {

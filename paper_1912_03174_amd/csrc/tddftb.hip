@@ -177,7 +177,8 @@ void inverse_overlap(td_ctx* c, bool warm = false) {
     if (res < 1e-15 || (res < 1e-9 && res >= 0.5 * prev)) break;
     prev = res;
     HIPCHK(c, td::two_minus(c->stream, c->A, np, n));                   // 2 - S X
-    gemm(c, 0, np, np, np, 1.0, c->Sinv, np, c->A, np, c->H, np);       // X (2 - S X)
+    // X (2 - S X) = 2 X - X S X is symmetric: the upper tiles and a mirror
+    HIPCHK(c, td::dgemm_symmetric(c->stream, np, np, c->Sinv, np, c->A, np, c->H, np));
     std::swap(c->Sinv, c->H);
     c->info.inverse_updates += 1;
     // The residual I - S X squares with each update: from a warm start below
