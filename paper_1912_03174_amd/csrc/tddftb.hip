@@ -441,18 +441,38 @@ void split_init(td_ctx* c) {
 }
 
 // One split-precision step body (after the dipole of rho_k is recorded):
-// potential change, sliced dH, B = S^-1 dH, sliced [A | B] and
-// [delta_re + renorm | -delta_im], X = A_ref rho_ref + [A | B][delta; rho_ref].
+// sliced [delta_re + renorm | -delta_im], potential change, sliced dH,
+// B = S^-1 dH, sliced [A | B], X = A_ref rho_ref + [A | B][delta; rho_ref].
 void split_products(td_ctx* c, const double* E, hipEvent_t* ev) {
   const int np = c->np, na = c->na;
   hipStream_t st = c->stream;
+  const int S = c->ns;
+  // [delta_re + renorm | -delta_im] (renormalises delta_re in place)
+  auto slice_density = [&] {
+    td::SliceSrc sdr;
+    sdr.M0 = c->rho_cur;
+    sdr.M0w = c->rho_cur;
+    sdr.ld0 = 2 * np;
+    sdr.M1 = c->rho_ref;
+    sdr.ld1 = np;
+    sdr.cs = c->scal + SC_RENORM;
+    slice(c, td::SLICE_RENORM, sdr, np, np, c->sl_R2, 2 * np * S, c->e_R2);
+    td::SliceSrc sdi;
+    sdi.M0 = c->rho_cur + np;
+    sdi.ld0 = 2 * np;
+    sdi.sign = -1.0;
+    slice(c, td::SLICE_PLAIN, sdi, np, np, c->sl_R2 + (size_t)np * 2 * np * S, 2 * np * S,
+          c->e_R2 + np);
+  };
+  // right after the charges pass has read the density, while its lines are
+  // still cached; the on-site correction reads the density first
+  if (c->plus_u == TD_PLUS_U_NONE) slice_density();
   HIPCHK(c, td::potential(st, c->gamma, c->dq, c->pos, E, c->orb_off, na, c->v, c->vorb,
                           c->v_ref));
   td::SliceSrc sdh;
   sdh.M0 = c->S;
   sdh.ld0 = np;
   sdh.v = c->vorb;
-  const int S = c->ns;
   if (c->plus_u != TD_PLUS_U_NONE) {
     // dH = 1/2 S o (dv + dv) + 1/2 (S dV + dV S) (Sec. 3.2) formed in A, then sliced
     block_pops(c, c->sh_n);
@@ -464,6 +484,7 @@ void split_products(td_ctx* c, const double* E, hipEvent_t* ev) {
     sa.M0 = c->A;
     sa.ld0 = np;
     slice(c, td::SLICE_PLAIN, sa, np, np, c->sl_dh, np * S, c->e_dh);
+    slice_density();
   } else {
     slice(c, td::SLICE_DH, sdh, np, np, c->sl_dh, np * S, c->e_dh);
   }
@@ -502,20 +523,6 @@ void split_products(td_ctx* c, const double* E, hipEvent_t* ev) {
     sb.ld0 = np;
     slice(c, td::SLICE_PLAIN, sb, np, np, c->sl_L2 + (size_t)np * S, 2 * np * S, c->e_L2 + np);
   }
-  td::SliceSrc sdr;
-  sdr.M0 = c->rho_cur;
-  sdr.M0w = c->rho_cur;
-  sdr.ld0 = 2 * np;
-  sdr.M1 = c->rho_ref;
-  sdr.ld1 = np;
-  sdr.cs = c->scal + SC_RENORM;
-  slice(c, td::SLICE_RENORM, sdr, np, np, c->sl_R2, 2 * np * S, c->e_R2);
-  td::SliceSrc sdi;
-  sdi.M0 = c->rho_cur + np;
-  sdi.ld0 = 2 * np;
-  sdi.sign = -1.0;
-  slice(c, td::SLICE_PLAIN, sdi, np, np, c->sl_R2 + (size_t)np * 2 * np * S, 2 * np * S,
-        c->e_R2 + np);
   td::SplitGemm g2;
   g2.m = np;
   g2.n = 2 * np;
