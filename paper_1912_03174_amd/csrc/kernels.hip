@@ -113,7 +113,8 @@ constexpr int TLD = TS + 1;
 
 enum { PAIR_LEAPFROG = 0, PAIR_HERM = 1, PAIR_SYM = 2 };
 
-// Block (bx, by) with by <= bx handles tiles (by, bx) and (bx, by).
+// Block k of the upper triangle of ntiles x ntiles tiles, row by row, handles
+// tiles (bi, bj) and (bj, bi), bi <= bj.
 // Thread t: row t/8 of the tile, 4 consecutive columns at 4*(t%8), moved as
 // two 16-byte pairs. Every global read of a thread (both tiles, and the
 // addend b of the leapfrog) is issued before its first write: the output
@@ -126,9 +127,15 @@ __global__ __launch_bounds__(256) void k_pair(const double* xre, const double* x
                                               const double* bre, const double* bim, int ldb,
                                               double* ore, double* oim, int ldo, double f,
                                               const double* xref, int ldr, const double* zre,
-                                              const double* zim, int ldz) {
-  const int bi = blockIdx.y, bj = blockIdx.x;
-  if (bi > bj) return;
+                                              const double* zim, int ldz, int ntiles) {
+  // row bi of the triangle starts at bi T - bi (bi - 1) / 2, T = ntiles
+  const int T = ntiles, k = blockIdx.x;
+  const double w = 2.0 * T + 1.0;
+  int bi = (int)((w - sqrt(w * w - 8.0 * k)) * 0.5);
+  bi = bi < 0 ? 0 : (bi >= T ? T - 1 : bi);
+  while (bi > 0 && bi * T - bi * (bi - 1) / 2 > k) --bi;
+  while (bi + 1 < T && (bi + 1) * T - (bi + 1) * bi / 2 <= k) ++bi;
+  const int bj = bi + (k - (bi * T - bi * (bi - 1) / 2));
   __shared__ double sre[2][TS][TLD];   // [0]: tile (bi,bj), [1]: tile (bj,bi)
   __shared__ double sim[2][TS][TLD];
   const int t = threadIdx.x;
@@ -637,31 +644,31 @@ hipError_t pair_leapfrog(hipStream_t s, const double* xre, const double* xim, in
                          const double* zre, const double* zim, int ldz) {
   if (np % TS) return hipErrorInvalidValue;
   if ((zre == nullptr) != (zim == nullptr)) return hipErrorInvalidValue;
-  const dim3 grid(np / TS, np / TS);
-  hipLaunchKernelGGL(k_pair<PAIR_LEAPFROG>, grid, dim3(256), 0, s, xre, xim, ldx, bre, bim, ldb,
-                     ore, oim, ldo, f, xref, ldr, zre, zim, ldz);
+  const int nt = np / TS;
+  hipLaunchKernelGGL(k_pair<PAIR_LEAPFROG>, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, xre, xim,
+                     ldx, bre, bim, ldb, ore, oim, ldo, f, xref, ldr, zre, zim, ldz, nt);
   return hipGetLastError();
 }
 
 hipError_t pair_herm(hipStream_t s, const double* tre, const double* tim, int ldt, double* ore,
                      double* oim, int ldo, int np) {
   if (np % TS) return hipErrorInvalidValue;
-  const dim3 grid(np / TS, np / TS);
-  hipLaunchKernelGGL(k_pair<PAIR_HERM>, grid, dim3(256), 0, s, tre, tim, ldt,
+  const int nt = np / TS;
+  hipLaunchKernelGGL(k_pair<PAIR_HERM>, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, tre, tim, ldt,
                      (const double*)nullptr, (const double*)nullptr, 0, ore, oim, ldo, 0.0,
                      (const double*)nullptr, 0, (const double*)nullptr, (const double*)nullptr,
-                     0);
+                     0, nt);
   return hipGetLastError();
 }
 
 hipError_t pair_sym(hipStream_t s, const double* t, int ldt, double* ore, double* oim, int ldo,
                     int np) {
   if (np % TS) return hipErrorInvalidValue;
-  const dim3 grid(np / TS, np / TS);
-  hipLaunchKernelGGL(k_pair<PAIR_SYM>, grid, dim3(256), 0, s, t, (const double*)nullptr, ldt,
-                     (const double*)nullptr, (const double*)nullptr, 0, ore, oim, ldo, 0.0,
-                     (const double*)nullptr, 0, (const double*)nullptr, (const double*)nullptr,
-                     0);
+  const int nt = np / TS;
+  hipLaunchKernelGGL(k_pair<PAIR_SYM>, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, t,
+                     (const double*)nullptr, ldt, (const double*)nullptr, (const double*)nullptr,
+                     0, ore, oim, ldo, 0.0, (const double*)nullptr, 0, (const double*)nullptr,
+                     (const double*)nullptr, 0, nt);
   return hipGetLastError();
 }
 
