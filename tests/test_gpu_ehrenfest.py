@@ -79,7 +79,7 @@ def test_trajectory_matches_oracle():
     ref = OE.propagate(s, m, rk, vel, n, 0.2, field=field)
     d_err = np.abs(mu - ref.dipoles).max() / np.abs(ref.dipoles - ref.dipoles[0]).max()
     say(f"dipole relative difference {d_err:.2e}")
-    assert d_err < 1e-8
+    assert d_err < 1e-10                 # the FP64 bar; measured 9e-14 to 9e-13
     assert np.abs(pos - ref.positions).max() < 1e-10
     assert np.abs(ek - ref.e_kin).max() < 1e-10 * ref.e_kin.max()
     assert np.abs(ee - ref.e_elec).max() < 1e-10 * np.abs(ref.e_elec).max()
@@ -107,7 +107,7 @@ def test_multi_tile_trajectory_matches_oracle():
     ref = OE.propagate(s, m, rk, vel, n, 0.2)
     d_err = np.abs(mu - ref.dipoles).max() / np.abs(ref.dipoles - ref.dipoles[0]).max()
     say(f"dipole relative difference {d_err:.2e}")
-    assert d_err < 1e-8
+    assert d_err < 1e-10                 # the FP64 bar; measured 9e-14 to 9e-13
     assert np.abs(pos - ref.positions).max() < 1e-10
     assert np.abs(rho - ref.rho).max() < 1e-10
     e.close()

@@ -8,7 +8,7 @@ td_set_rho and N-1 steps with the fields of t_{N-1} .. t_1 must return
 conj rho_0, to rounding in FP64. The split-BF16 path reverses to the
 accuracy of its products (each carries a relative error of about 2^-32 of
 the departure from the reference, accumulated over 2N steps), well within
-its admissible 1e-6 of the signal. The largest case is the 4096-orbital
+an order below its admissible 1e-6 of the signal. The largest case is the 4096-orbital
 strip of the benchmark.
 """
 import sys
@@ -60,8 +60,9 @@ def test_leapfrog_reverses(which, precision):
     travelled = np.abs(rho_n - rho0).max()
     say(f"reversal error {err:.3e}, kick signal {signal:.3e}, change over the run {travelled:.3e}")
     assert travelled > 3 * signal           # the field moved the state well away from rho0
-    # FP64: rounding only. Split-BF16: within the form's admissible error,
-    # 1e-6 of the signal (the dipole bound the split products are held to);
-    # measured 1.7e-9 (112 and 648 orbitals) to 1.3e-8 (4096) of it.
-    assert err < (1e-11 if precision == "fp64" else 1e-6 * travelled)
+    # FP64: rounding only. Split-BF16: the products' error accumulated over
+    # 2N steps, measured 1.7e-9 (112 and 648 orbitals) to 1.3e-8 (4096) of
+    # the change; held to 1e-7 of it, an order below the form's admissible
+    # 1e-6 of the signal.
+    assert err < (1e-11 if precision == "fp64" else 1e-7 * travelled)
     p.close()

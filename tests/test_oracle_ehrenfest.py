@@ -54,12 +54,12 @@ def test_fd_gradient_matches_analytic_two_centre_derivatives(benzene):
     assert worst < 1e-8
 
 
-def _scc_energy(s, m, positions):
+def _scc_energy(s, m, positions, field=None):
     S, H0 = OE.model_matrices(m, positions)
     gamma = OE.gamma_matrix(positions, m["hubbard_u"])
     sys2 = dataclasses.replace(s, positions=positions, S=S, H0=H0, gamma=gamma)
-    gs = O.ground_state(sys2, tol=1e-13)
-    return gs, sys2, O.energy(gs.rho, H0, gamma, gs.dq, positions)
+    gs = O.ground_state(sys2, tol=1e-13, field=field)
+    return gs, sys2, O.energy(gs.rho, H0, gamma, gs.dq, positions, field)
 
 
 def test_ground_state_force_is_minus_energy_gradient(benzene):
@@ -84,6 +84,60 @@ def test_ground_state_force_is_minus_energy_gradient(benzene):
         num = -(ep - em) / (2 * h)
         assert abs(F[a, k] - num) < 1e-5 * np.abs(F).max() + 1e-9, (a, k, F[a, k], num)
     assert np.abs(F.sum(axis=0)).max() < 1e-10 * np.abs(F).max()
+
+
+def test_ground_state_force_in_a_static_field(benzene):
+    """In a static uniform field the SCC ground state minimises
+    E = E_band + E_coul + sum_A dq_A R_A . E (Eq. 7 and the relation after
+    Eq. 15), so the force of Eq. 15 with its field term -dq_A E equals -dE/dR
+    by central differences. The field term is 4e-3 to 1.5e-2 here against a
+    central-difference error below 1e-7: either sign of it, or leaving it out,
+    fails. The forces still sum to -sum_A dq_A E = 0 for a neutral system."""
+    s, m = benzene
+    field = np.array([0.03, -0.02, 0.0])
+    gs, sys0, _ = _scc_energy(s, m, s.positions, field)
+    S, H0 = sys0.S, sys0.H0
+    Sinv = O.inverse_overlap(S)
+    GS, GH = OE.fd_gradients(m, s.positions)
+    atom_of, _ = OE.orbital_types(m)
+    v_orb = (sys0.gamma @ gs.dq + s.positions @ field)[atom_of]
+    H = H0 + 0.5 * S * (v_orb[:, None] + v_orb[None, :])
+    F = OE.forces(gs.rho, H, Sinv, GS, GH, v_orb, gs.dq, s.positions, m["hubbard_u"], field, m)
+    h = 1e-3
+    checked = 0
+    for a, k in [(0, 0), (2, 1), (7, 0), (3, 1), (9, 0)]:
+        p = s.positions.copy()
+        p[a, k] += h
+        ep = _scc_energy(s, m, p, field)[2]
+        p[a, k] -= 2 * h
+        em = _scc_energy(s, m, p, field)[2]
+        num = -(ep - em) / (2 * h)
+        assert abs(F[a, k] - num) < 1e-6 * np.abs(F).max(), (a, k, F[a, k], num)
+        checked += abs(gs.dq[a] * field[k]) > 1e-3
+    assert checked >= 3                                   # the field term is visible
+    assert np.abs(F.sum(axis=0)).max() < 1e-10 * np.abs(F).max()
+
+
+def test_total_energy_conserved_in_a_constant_field(benzene):
+    """Under a constant field the Hamiltonian does not depend on time, so
+    electronic energy (with its sum_A dq_A R_A . E term) plus nuclear kinetic
+    energy is conserved. Started from the SCC ground state in the field with
+    thermal nuclei (2000 K), the total stays within 4.3e-6 Ha at dt = 0.2 and
+    0.1 (the velocity-dependent force terms, dropped as in the paper, leave
+    this dt-independent remainder) while 0.11 Ha of kinetic energy swings;
+    the field force on the charges (-dq_A E, Eq. 15) with the other sign
+    lets it drift by 2.2e-4."""
+    s, m = benzene
+    field = np.array([0.03, 0.02, 0.0])
+    gs = O.ground_state(s, tol=1e-13, field=field)
+    vel = W.thermal_velocities(s, 2000.0, seed=5)
+    for dt, n in ((0.2, 200), (0.1, 400)):
+        tr = OE.propagate(s, m, gs.rho.astype(np.complex128), vel, n, dt,
+                          field=np.tile(field, (n, 1)))
+        etot = tr.e_elec + tr.e_kin
+        swing = np.abs(tr.e_kin - tr.e_kin[0]).max()
+        assert swing > 5e-2
+        assert np.abs(etot - etot[0]).max() < 2e-5, dt
 
 
 def test_total_energy_conserved(benzene):
