@@ -57,7 +57,9 @@ typedef enum {
   TD_EHIP = -3,         /* HIP runtime error (message has the HIP text)    */
   TD_ENOTPOSDEF = -4,   /* S is not positive definite (inverse diverged)   */
   TD_ESCF = -5,         /* ground state: SCC or purification not converged */
-  TD_EUNSTABLE = -6,    /* non-finite values after a step                  */
+  TD_EUNSTABLE = -6,    /* leapfrog unstable: dt too large for the spectrum
+                           of S^-1 H, or the state became non-finite, or
+                           its electron count Tr(rho S) drifted            */
   TD_ENOTSUP = -7,      /* feature not available in this library           */
   TD_ESTATE = -8        /* call not valid in the context's current state   */
 } td_status;
@@ -132,6 +134,11 @@ typedef struct {
   int32_t mix_history;         /* ground state: Anderson history (1..8)         */
   int32_t profile;             /* 1: time kernel classes with HIP events        */
   void *hip_stream;            /* hipStream_t to use, or NULL for an own stream */
+  int32_t n_slices_dh;         /* split-bf16: slices of the S^-1 dH product     */
+                               /* (3 .. n_slices), 0: n_slices. That product    */
+                               /* carries only the change of H from the         */
+                               /* reference, so its rounding enters the density */
+                               /* scaled by that change                          */
 } td_options;
 
 /* Statistics of the initialisation. */
@@ -149,6 +156,15 @@ typedef struct {
   int32_t precision;
   int64_t inverse_updates;            /* Newton-Schulz updates of S^-1 since creation
                                          (moving nuclei: along the trajectory) */
+  double width_estimate;              /* lower bound of the width of the spectrum of
+                                         S^-1 H of the initial state at zero field
+                                         (Rayleigh quotients after power iteration) */
+  double stability;                   /* dt * width_estimate; td_step refuses to run
+                                         (TD_EUNSTABLE) unless it is below 1, the
+                                         leapfrog limit (Sec. 2.3, Eq. 19)           */
+  int64_t inverse_restarts;           /* moving nuclei: Newton-Schulz iterations begun
+                                         again from the scaled identity after a poor
+                                         start along the trajectory                  */
 } td_info;
 
 /* Kernel classes timed when td_options.profile = 1. In split-bf16
@@ -165,7 +181,7 @@ enum {
 
 /* Fills *opt with defaults: FP64, 4 slices, dt = 0.2, scc_tol = 1e-12,
  * scc_maxiter = 300, mix_beta = 0.3, mix_history = 8, profile = 0, own
- * stream. */
+ * stream, n_slices_dh = 0. */
 TD_API void td_default_options(td_options *opt);
 
 /* Creates a context (Sec. 2.3): copies the model to the GPU, forms S^-1,
@@ -186,8 +202,14 @@ TD_API td_status td_kick(td_ctx *ctx, double e0, const double dir[3]);
 /* Advances n >= 0 steps of dt (Sec. 2.3, Eq. 19). field is NULL (no
  * field) or [n * 3]: field[3k..3k+2] = E(t) at the time of the k-th
  * density matrix of this call. The dipole of each density entering a
- * step is recorded (see td_get_dipole_series). Returns TD_EUNSTABLE if
- * the state became non-finite. */
+ * step is recorded (see td_get_dipole_series). Returns TD_EUNSTABLE
+ * before any step when dt times the width of the spectrum of S^-1 H (a
+ * lower bound taken at creation, td_info.width_estimate) is 1 or more,
+ * where the leapfrog diverges (Sec. 2.3, Eq. 19); and after the steps if
+ * the state became non-finite or its electron count Tr(rho S), which the
+ * leapfrog keeps, moved by more than 1e-6 N_e since creation, the last
+ * kick or restore (1e-3 N_e with moving nuclei; in split-bf16 precision,
+ * which restores the count every step, within the last step). */
 TD_API td_status td_step(td_ctx *ctx, int32_t n, const double *field);
 
 /* Mulliken charge fluctuations dq [n_atoms] of the current rho (Eq. 5). */
@@ -345,8 +367,9 @@ TD_API td_status td_batch_kick(td_batch *b, const double *e0, const double *dir)
 
 /* Advances every member n >= 0 steps (Sec. 2.3, Eq. 19); field is NULL or
  * [n * 3], the same field for all members. Records each member's dipole of
- * each density entering a step. TD_EUNSTABLE names the first non-finite
- * member. */
+ * each density entering a step. TD_EUNSTABLE (as for td_step: the leapfrog
+ * limit before any step, then a non-finite state or a drifted electron
+ * count) names the first member concerned. */
 TD_API td_status td_batch_step(td_batch *b, int32_t n, const double *field);
 
 /* Per-member results, as the td_get_* calls of a solo context. */

@@ -371,6 +371,16 @@ void create_impl(td_batch* b, int n, const td_system* systems, const td_options*
 
 void step_impl(td_batch* b, int n, const double* field) {
   REQUIRE(b, n >= 0, TD_EINVAL, "n must be >= 0");
+  // the leapfrog limit of each member (Sec. 2.3, Eq. 19), as a solo td_step checks it
+  for (int m = 0; m < b->nm; ++m) {
+    const td_ctx* c = b->mem[m];
+    if (!(c->info.stability < 1.0)) {
+      b->err = "member " + std::to_string(m) + ": time step " + std::to_string(c->opt.dt) +
+               " too large for the leapfrog: dt times the width of the spectrum of S^-1 H is " +
+               std::to_string(c->info.stability) + " (must be below 1)";
+      throw Fail{TD_EUNSTABLE};
+    }
+  }
   if (n == 0) {
     b->last_n = 0;     // an empty call records no dipoles
     return;

@@ -243,6 +243,16 @@ hipError_t gershgorin(hipStream_t s, const double* T, int ld, int n, double* wor
 // out[0] = sum_i x[i]
 hipError_t sum_vector(hipStream_t s, const double* x, int n, double* out);
 
+// Power iteration on column blocks (V, W, SV: np x ncols, leading dimension
+// ld). power_start: +-1 entries in rows < n, zero in the padding rows.
+// power_step: columns j < half become (W - lo V) / |W - lo V|, the others
+// (hi V - W) / |hi V - W|. rayleigh: out[j] = (SV_j . W_j) / (SV_j . V_j).
+hipError_t power_start(hipStream_t s, double* V, int ld, int n, int np, int ncols);
+hipError_t power_step(hipStream_t s, const double* W, double* V, int ld, int np, int ncols,
+                      int half, double lo, double hi);
+hipError_t rayleigh(hipStream_t s, const double* V, const double* W, const double* SV, int ld,
+                    int np, int ncols, double* out);
+
 // Anderson mixing of SCC charges: r = dq_out - dq_in, out_resid[0] = max|r|;
 // history slot `slot` <- (dq_in, r); `count` valid entries after storing;
 // dq_in <- Anderson update with parameter beta.

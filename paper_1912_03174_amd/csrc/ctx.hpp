@@ -42,12 +42,14 @@ struct td_ctx {
   double mu_h[3] = {0, 0, 0};
   int64_t step = 0;
   bool has_prev = false;
+  double ne_ref = 0.0;         // Tr(rho S) when the state was last set (creation, kick, restore)
   int last_n = 0;
   td_info info{};
   std::string err;
   // split-bf16 precision: the state buffers hold rho - rho_ref
   bool split = false;
-  int ns = 4;
+  int ns = 4;                  // slices of [S^-1 H | S^-1 dH] [rho - rho_ref ; rho_ref]
+  int ns1 = 4;                 // slices of S^-1 dH
   double *rho_ref = nullptr;   // np x np real reference density (the initial state)
   double *Agsb = nullptr;      // S^-1 H_ref
   double *Xref = nullptr;      // np x 2np wide: (S^-1 H_ref) rho_ref | 0

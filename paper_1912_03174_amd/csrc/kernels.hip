@@ -583,6 +583,63 @@ __global__ void k_vec_add(const double* __restrict__ a, const double* __restrict
   if (i < n) out[i] = a[i] + b[i];
 }
 
+// ------------------------------------------------------------------ spectral width
+// Start block of the power iteration: +-1 from a hash of (row, column) in
+// the first n rows, zero in the padding rows.
+__global__ void k_power_start(double* __restrict__ V, int ld, int n, int np, int ncols) {
+  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (size_t)np * ncols) return;
+  const int r = (int)(idx / ncols), j = (int)(idx % ncols);
+  unsigned h = (unsigned)r * 2654435761u ^ ((unsigned)j * 40503u + 0x9e3779b9u);
+  h ^= h >> 15;
+  h *= 0x2c1b3c6du;
+  h ^= h >> 12;
+  V[(size_t)r * ld + j] = r < n ? ((h & 1u) ? 1.0 : -1.0) : 0.0;
+}
+
+// One block per column j: U = W - lo V (j < half) or hi V - W (j >= half),
+// then V = U / |U|. Each element is read and rewritten by the same thread,
+// after the block's norm is complete.
+__global__ __launch_bounds__(1024) void k_power_step(const double* __restrict__ W,
+                                                     double* __restrict__ V, int ld, int np,
+                                                     int half, double lo, double hi) {
+  __shared__ double sh[17];
+  const int j = blockIdx.x;
+  const bool top = j < half;
+  double ss = 0.0;
+  for (int r = threadIdx.x; r < np; r += 1024) {
+    const size_t o = (size_t)r * ld + j;
+    const double u = top ? W[o] - lo * V[o] : hi * V[o] - W[o];
+    ss += u * u;
+  }
+  ss = block_sum_1024(ss, sh);
+  const double inv = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+  for (int r = threadIdx.x; r < np; r += 1024) {
+    const size_t o = (size_t)r * ld + j;
+    const double u = top ? W[o] - lo * V[o] : hi * V[o] - W[o];
+    V[o] = u * inv;
+  }
+}
+
+// Generalized Rayleigh quotient of each column: W = T V with T = S^-1 H
+// and SV = S V give x^T H x / x^T S x = (SV . W) / (SV . V).
+__global__ __launch_bounds__(1024) void k_rayleigh(const double* __restrict__ V,
+                                                   const double* __restrict__ W,
+                                                   const double* __restrict__ SV, int ld, int np,
+                                                   double* __restrict__ out) {
+  __shared__ double sh[17];
+  const int j = blockIdx.x;
+  double num = 0.0, den = 0.0;
+  for (int r = threadIdx.x; r < np; r += 1024) {
+    const size_t o = (size_t)r * ld + j;
+    num += SV[o] * W[o];
+    den += SV[o] * V[o];
+  }
+  num = block_sum_1024(num, sh);
+  den = block_sum_1024(den, sh);
+  if (threadIdx.x == 0) out[j] = num / den;
+}
+
 inline unsigned blocks_for(size_t n, int per = 256) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -780,6 +837,24 @@ hipError_t energy_terms(hipStream_t s, const double* band_rows, int n, const dou
                         double* out) {
   hipLaunchKernelGGL(k_energy, dim3(1), dim3(1024), 0, s, band_rows, n, dq, v_gamma, pos, E, na,
                      out);
+  return hipGetLastError();
+}
+
+hipError_t power_start(hipStream_t s, double* V, int ld, int n, int np, int ncols) {
+  hipLaunchKernelGGL(k_power_start, dim3(blocks_for((size_t)np * ncols)), dim3(256), 0, s, V, ld,
+                     n, np, ncols);
+  return hipGetLastError();
+}
+
+hipError_t power_step(hipStream_t s, const double* W, double* V, int ld, int np, int ncols,
+                      int half, double lo, double hi) {
+  hipLaunchKernelGGL(k_power_step, dim3(ncols), dim3(1024), 0, s, W, V, ld, np, half, lo, hi);
+  return hipGetLastError();
+}
+
+hipError_t rayleigh(hipStream_t s, const double* V, const double* W, const double* SV, int ld,
+                    int np, int ncols, double* out) {
+  hipLaunchKernelGGL(k_rayleigh, dim3(ncols), dim3(1024), 0, s, V, W, SV, ld, np, out);
   return hipGetLastError();
 }
 

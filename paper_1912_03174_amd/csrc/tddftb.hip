@@ -117,16 +117,46 @@ void mulliken(td_ctx* c, double* mu) {
   }
 }
 
-// Observables of the current state, copied to the host; checks finiteness.
-void refresh(td_ctx* c) {
+// Observables of the current state, copied to the host; checks finiteness
+// and the electron count Tr(rho S), a constant of the leapfrog motion
+// (Sec. 2.3). `reference`: the state was just set (creation, kick,
+// restore) and its count becomes the one later states are held to.
+// Otherwise a count that moved by more than 1e-6 N_e (1e-3 N_e with moving
+// nuclei, where S changes and leapfrog keeps the count only to its own
+// error) is reported as an unstable run; in split-bf16 precision, where
+// every step restores the count, the departure of the last step is checked.
+void refresh(td_ctx* c, bool reference = false) {
   mulliken(c, c->scal + SC_MU);
   c->dq_h.resize(c->na);
   HIPCHK(c, hipMemcpyAsync(c->dq_h.data(), c->dq, sizeof(double) * c->na, hipMemcpyDeviceToHost,
                            c->stream));
-  read_scal(c, SC_MU, c->mu_h, 3);
+  double sc[4];                            // dipole, electron count (FP64 path)
+  read_scal(c, SC_MU, sc, 4);
+  std::memcpy(c->mu_h, sc, sizeof(c->mu_h));
   bool ok = std::isfinite(c->mu_h[0]) && std::isfinite(c->mu_h[1]) && std::isfinite(c->mu_h[2]);
   for (int a = 0; a < c->na && ok; ++a) ok = std::isfinite(c->dq_h[a]);
   REQUIRE(c, ok, TD_EUNSTABLE, "density matrix became non-finite (time step too large?)");
+  double ne = sc[3];
+  if (c->split) {
+    double cr;
+    read_scal(c, SC_RENORM, &cr, 1);
+    ne = c->nelec * (1.0 + cr);
+  }
+  REQUIRE(c, std::isfinite(ne), TD_EUNSTABLE, "electron count became non-finite");
+  if (reference) {
+    c->ne_ref = ne;
+    return;
+  }
+  const double tol = (c->ehr ? 1e-3 : 1e-6) * c->nelec;
+  const double drift = c->split ? std::fabs(ne - c->nelec) : std::fabs(ne - c->ne_ref);
+  if (!(drift <= tol)) {
+    char msg[200];
+    std::snprintf(msg, sizeof(msg),
+                  "electron count Tr(rho S) = %.12g moved by %.3g from %.12g by step %lld "
+                  "(unstable run?)",
+                  ne, drift, c->split ? (double)c->nelec : c->ne_ref, (long long)c->step);
+    REQUIRE(c, false, TD_EUNSTABLE, msg);
+  }
 }
 
 // S^-1 by the Newton-Schulz iteration X <- X (2 - S X), X_0 = I / g with g
@@ -167,11 +197,28 @@ void inverse_overlap(td_ctx* c, bool warm = false) {
     HIPCHK(c, td::scaled_identity(c->stream, c->Sinv, np, n, 1.0 / b[1]));
   }
   double prev = INFINITY, res = INFINITY;
+  bool restarted = false;
   int it = 0;
   for (it = 1; it <= 200; ++it) {
     gemm(c, 0, np, np, np, 1.0, c->S, np, c->Sinv, np, c->A, np);     // T = S X
     HIPCHK(c, td::identity_residual(c->stream, c->A, np, n, c->work1, c->scal + SC_RES));
     read_scal(c, SC_RES, &res, 1);
+    // A warm start converges only while the spectral radius of 1 - S X is
+    // below 1, which the element-wise residual does not bound: after a long
+    // nuclear step (a start residual above 1/4) or a residual that grows,
+    // begin again from the scaled identity, which always converges.
+    if (warm && !restarted && !(res <= 0.25 && res < prev)) {
+      HIPCHK(c, td::gershgorin(c->stream, c->S, np, n, c->work1, c->work2, c->scal + SC_BOUNDS));
+      double b[2];
+      read_scal(c, SC_BOUNDS, b, 2);
+      REQUIRE(c, std::isfinite(b[1]) && b[1] > 0, TD_ENOTPOSDEF,
+              "S has no positive spectrum bound");
+      HIPCHK(c, td::scaled_identity(c->stream, c->Sinv, np, n, 1.0 / b[1]));
+      restarted = true;
+      prev = INFINITY;
+      c->info.inverse_restarts += 1;
+      continue;
+    }
     REQUIRE(c, std::isfinite(res) && res < 1e3, TD_ENOTPOSDEF,
             "S is not positive definite: inverse iteration diverged");
     if (res < 1e-15 || (res < 1e-9 && res >= 0.5 * prev)) break;
@@ -353,6 +400,9 @@ void validate(td_ctx* c, const td_system* s, const td_options* o) {
   validate_plus_u(c, s);
   REQUIRE(c, o->precision == TD_FP64 || (o->n_slices >= 3 && o->n_slices <= 5), TD_EINVAL,
           "n_slices must be 3, 4 or 5");
+  REQUIRE(c, o->precision == TD_FP64 || o->n_slices_dh == 0 ||
+                 (o->n_slices_dh >= 3 && o->n_slices_dh <= o->n_slices),
+          TD_EINVAL, "n_slices_dh must be 0 or 3 .. n_slices");
   REQUIRE(c, o->scc_tol > 0 && o->scc_maxiter > 0 && o->mix_beta > 0 && o->mix_beta <= 1,
           TD_EINVAL, "invalid SCC options");
   const size_t n = (size_t)s->n_orb, na = (size_t)s->n_atoms;
@@ -382,8 +432,8 @@ void ialloc(td_ctx* c, int** p, size_t count) {
 }
 
 void slice(td_ctx* c, int mode, const td::SliceSrc& src, int rows, int cols, __bf16* out,
-           int ldo, int* exps) {
-  HIPCHK(c, td::slice_rows(c->stream, c->ns, mode, src, rows, cols, out, ldo, exps));
+           int ldo, int* exps, int ns = 0) {
+  HIPCHK(c, td::slice_rows(c->stream, ns ? ns : c->ns, mode, src, rows, cols, out, ldo, exps));
 }
 
 // Split precision set-up. The current (full) density becomes the reference
@@ -430,7 +480,7 @@ void split_init(td_ctx* c) {
   si.M0 = c->Sinv;
   si.ld0 = np;
   const int S = c->ns;
-  slice(c, td::SLICE_PLAIN, si, np, np, c->sl_sinv, np * S, c->e_sinv);
+  slice(c, td::SLICE_PLAIN, si, np, np, c->sl_sinv, np * c->ns1, c->e_sinv, c->ns1);
   td::SliceSrc sr;
   sr.M0 = c->rho_ref;
   sr.ld0 = np;
@@ -446,7 +496,7 @@ void split_init(td_ctx* c) {
 void split_products(td_ctx* c, const double* E, hipEvent_t* ev) {
   const int np = c->np, na = c->na;
   hipStream_t st = c->stream;
-  const int S = c->ns;
+  const int S = c->ns, S1 = c->ns1;    // slices of the second and of the first product
   // [delta_re + renorm | -delta_im] (renormalises delta_re in place)
   auto slice_density = [&] {
     td::SliceSrc sdr;
@@ -483,19 +533,19 @@ void split_products(td_ctx* c, const double* E, hipEvent_t* ev) {
     td::SliceSrc sa;
     sa.M0 = c->A;
     sa.ld0 = np;
-    slice(c, td::SLICE_PLAIN, sa, np, np, c->sl_dh, np * S, c->e_dh);
+    slice(c, td::SLICE_PLAIN, sa, np, np, c->sl_dh, np * S1, c->e_dh, S1);
     slice_density();
   } else {
-    slice(c, td::SLICE_DH, sdh, np, np, c->sl_dh, np * S, c->e_dh);
+    slice(c, td::SLICE_DH, sdh, np, np, c->sl_dh, np * S1, c->e_dh, S1);
   }
   td::SplitGemm g1;
   g1.m = np;
   g1.n = np;
   g1.L = c->sl_sinv;
-  g1.ldl = np * S;
+  g1.ldl = np * S1;
   g1.eL = c->e_sinv;
   g1.R = c->sl_dh;
-  g1.ldr = np * S;
+  g1.ldr = np * S1;
   g1.fR = c->e_dh;
   g1.seg_len = np;
   g1.k_lo = np;
@@ -504,7 +554,7 @@ void split_products(td_ctx* c, const double* E, hipEvent_t* ev) {
   g1.C = c->H;            // B = S^-1 dH
   g1.ldc = np;
   if (ev) HIPCHK(c, hipEventRecord(ev[1], st));
-  HIPCHK(c, td::split_gemm(st, c->ns, g1));
+  HIPCHK(c, td::split_gemm(st, S1, g1));
   if (ev) HIPCHK(c, hipEventRecord(ev[2], st));
   td::SliceSrc sa;
   sa.M0 = c->Agsb;
@@ -666,6 +716,58 @@ void block_pops(td_ctx* c, double* out, const double* rho, int ldr) {
                                   c->max_shell, c->plus_u, c->np, out, c->sh_e));
 }
 
+// Lower bound of the width of the spectrum of S^-1 H (the generalized
+// eigenvalues of (H, S)) of the current state at zero field. The leapfrog
+// step multiplies the (i, j) element of rho in the generalized eigenbasis
+// by the roots of z^2 + 2 i theta z - 1 with theta = dt (eps_i - eps_j),
+// which leave the unit circle once |theta| > 1 (Sec. 2.3, Eq. 19). Every
+// Rayleigh quotient x^T H x / x^T S x lies between the extreme eigenvalues,
+// so the largest quotient of 64 vectors steered to the top of the spectrum
+// by power iteration with S^-1 H - lo, minus the smallest of 64 steered to
+// its bottom with hi - S^-1 H (lo, hi: Gershgorin bounds), never exceeds
+// the width; after 80 steps it is within a few percent of it.
+void spectral_width(td_ctx* c) {
+  constexpr int kCols = 128, kIters = 80;
+  const int n = c->n, np = c->np, na = c->na;
+  hipStream_t st = c->stream;
+  HIPCHK(c, td::potential(st, c->gamma, c->dq, c->pos, nullptr, c->orb_off, na, c->v, c->vorb));
+  if (c->plus_u != TD_PLUS_U_NONE) block_pops(c, c->sh_n);
+  assemble_hamiltonian(c, c->sh_n);
+  gemm(c, 0, np, np, np, 1.0, c->Sinv, np, c->H, np, c->A, np);        // T = S^-1 H
+  HIPCHK(c, td::gershgorin(st, c->A, np, n, c->work1, c->work2, c->scal + SC_BOUNDS));
+  double b[2];
+  read_scal(c, SC_BOUNDS, b, 2);
+  REQUIRE(c, std::isfinite(b[0]) && std::isfinite(b[1]), TD_EUNSTABLE,
+          "non-finite Hamiltonian: no spectrum bounds");
+  // np x 128 blocks in buffers that hold nothing yet: X (np x 2np) and rho_prev
+  double* V = c->X;
+  double* Wb = c->X + (size_t)np * kCols;
+  double* SV = c->rho_prev;
+  HIPCHK(c, td::power_start(st, V, kCols, n, np, kCols));
+  for (int k = 0; k < kIters; ++k) {
+    gemm(c, 0, np, kCols, np, 1.0, c->A, np, V, kCols, Wb, kCols);
+    HIPCHK(c, td::power_step(st, Wb, V, kCols, np, kCols, kCols / 2, b[0], b[1]));
+  }
+  gemm(c, 0, np, kCols, np, 1.0, c->A, np, V, kCols, Wb, kCols);
+  gemm(c, 0, np, kCols, np, 1.0, c->S, np, V, kCols, SV, kCols);
+  HIPCHK(c, td::rayleigh(st, V, Wb, SV, kCols, np, kCols, c->work1));
+  std::vector<double> r(kCols);
+  HIPCHK(c, hipMemcpyAsync(r.data(), c->work1, sizeof(double) * kCols, hipMemcpyDeviceToHost, st));
+  sync(c);
+  double top = -INFINITY, bottom = INFINITY;
+  for (int j = 0; j < kCols / 2; ++j) top = std::max(top, r[j]);
+  for (int j = kCols / 2; j < kCols; ++j) bottom = std::min(bottom, r[j]);
+  REQUIRE(c, std::isfinite(top) && std::isfinite(bottom), TD_EUNSTABLE,
+          "non-finite Rayleigh quotients of S^-1 H");
+  c->info.width_estimate = std::max(top - bottom, 0.0);
+  c->info.stability = c->opt.dt * c->info.width_estimate;
+  // X and rho_prev served as scratch: back to zeros (no leapfrog history
+  // exists yet, and kernels that cover only the n x n block rely on the
+  // padding being zero)
+  HIPCHK(c, hipMemsetAsync(c->rho_prev, 0, sizeof(double) * 2 * (size_t)np * np, st));
+  HIPCHK(c, hipMemsetAsync(c->X, 0, sizeof(double) * 2 * (size_t)np * np, st));
+}
+
 void create_impl(td_ctx* c, const td_system* s_in, const td_options* o) {
   REQUIRE(c, s_in && o, TD_EINVAL, "null system or options");
   REQUIRE(c, (s_in->flags & ~TD_DEVICE_PTRS) == 0, TD_EINVAL, "unknown td_system flags");
@@ -688,6 +790,7 @@ void create_impl(td_ctx* c, const td_system* s_in, const td_options* o) {
   // inverse run in FP64 and need the reference buffers not yet allocated.
   const bool want_split = o->precision == TD_SPLIT_BF16;
   c->ns = o->n_slices;
+  c->ns1 = o->n_slices_dh ? o->n_slices_dh : o->n_slices;
   // split products accumulate exactly over 256-long K chunks
   c->np = round_up(s->n_orb, want_split ? 256 : td::kPad);
   if (s->occ) {
@@ -752,13 +855,15 @@ void create_impl(td_ctx* c, const td_system* s_in, const td_options* o) {
   } else {
     ground_state(c);
   }
+  refresh(c, true);                        // charges of the initial state
+  spectral_width(c);
   if (want_split) {
     split_init(c);
     c->split = true;
   }
   c->step = 0;
   c->has_prev = false;
-  refresh(c);
+  refresh(c, true);
 }
 
 // ---------------------------------------------------------------- moving nuclei
@@ -843,6 +948,14 @@ void ehr_step(td_ctx* c, int k, const double* E) {
 
 void step_impl(td_ctx* c, int nsteps, const double* field) {
   REQUIRE(c, nsteps >= 0, TD_EINVAL, "n must be >= 0");
+  if (!(c->info.stability < 1.0)) {
+    char msg[200];
+    std::snprintf(msg, sizeof(msg),
+                  "time step %.4g too large for the leapfrog: the spectrum of S^-1 H is at least "
+                  "%.4g wide, and dt times that width is %.3g (must be below 1)",
+                  c->opt.dt, c->info.width_estimate, c->info.stability);
+    REQUIRE(c, false, TD_EUNSTABLE, msg);
+  }
   if (nsteps == 0) {
     c->last_n = 0;     // an empty call records no dipoles (or energies)
     return;
@@ -968,7 +1081,7 @@ void kick_impl(td_ctx* c, double e0, const double* dir) {
   if (c->split) HIPCHK(c, td::wide_add_real(c->stream, c->rho_cur, c->rho_ref, np, -1.0));
   c->has_prev = false;
   sync(c);
-  refresh(c);
+  refresh(c, true);
 }
 
 // Host-pointer split-bf16 product for td_util_gemm: A rows and B columns
@@ -1181,7 +1294,7 @@ void create_ehr_impl(td_ctx* c, const td_system* s, const td_model* m, const dou
   c->vel_half = false;
   rebuild_model(c, true);
   c->sinv_hist = 0;   // that refinement is at the starting positions: no trajectory yet
-  refresh(c);
+  refresh(c, true);
 }
 
 }  // namespace
@@ -1354,7 +1467,7 @@ td_status td_set_rho(td_ctx* ctx, const double* rho, const double* rho_prev, int
     c->has_prev = rho_prev != nullptr;
     c->step = step;
     sync(c);
-    refresh(c);
+    refresh(c, true);
   });
 }
 

@@ -54,7 +54,7 @@ class TdOptions(ctypes.Structure):
                 ("dt", ctypes.c_double), ("scc_tol", ctypes.c_double),
                 ("scc_maxiter", ctypes.c_int32), ("mix_beta", ctypes.c_double),
                 ("mix_history", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("hip_stream", ctypes.c_void_p)]
+                ("hip_stream", ctypes.c_void_p), ("n_slices_dh", ctypes.c_int32)]
 
 
 class TdInfo(ctypes.Structure):
@@ -65,7 +65,9 @@ class TdInfo(ctypes.Structure):
                 ("purification_error", ctypes.c_double),
                 ("spectrum_lo", ctypes.c_double), ("spectrum_hi", ctypes.c_double),
                 ("step", ctypes.c_int64), ("has_prev", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("inverse_updates", ctypes.c_int64)]
+                ("precision", ctypes.c_int32), ("inverse_updates", ctypes.c_int64),
+                ("width_estimate", ctypes.c_double), ("stability", ctypes.c_double),
+                ("inverse_restarts", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -511,11 +513,12 @@ class Propagator:
 
     def __init__(self, system, dt=0.2, precision=TD_FP64, n_slices=4, rho0=None, occ=None,
                  profile=False,
-                 scc_tol=1e-12, scc_maxiter=300, plus_u=None):
+                 scc_tol=1e-12, scc_maxiter=300, plus_u=None, n_slices_dh=0):
         opt = td_default_options()
         opt.dt = dt
         opt.precision = precision
         opt.n_slices = n_slices
+        opt.n_slices_dh = n_slices_dh
         opt.profile = 1 if profile else 0
         opt.scc_tol = scc_tol
         opt.scc_maxiter = scc_maxiter

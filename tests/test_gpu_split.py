@@ -132,8 +132,11 @@ def test_split_full_size_one_step_sampled_rows(cfg):
     r1, i1 = W.random_hermitian_pair(n, seed=41, scale=1e-3, base=np.eye(n))
     r0, i0 = W.random_hermitian_pair(n, seed=42, scale=1e-3, base=np.eye(n))
     cur, prev = r1 + 1j * i1, r0 + 1j * i0
-    # exact electron count, so the split path's trace renormalisation is a no-op
+    # exact electron count in both, as for a physical history: the split
+    # path's trace renormalisation is a no-op, and the count the leapfrog
+    # carries forward from prev is the one the library holds the run to
     cur *= s.n_elec / np.sum(cur.real * s.S)
+    prev *= s.n_elec / np.sum(prev.real * s.S)
     E = np.array([[0.0, 0.004, 0.0]])
     p = T.Propagator(s, rho0=cur, precision=T.TD_SPLIT_BF16, n_slices=4)
     p.set_rho(cur, prev, 10)

@@ -1,0 +1,143 @@
+"""Failure detection on the GPU: the leapfrog limit checked before any step,
+the electron count Tr(rho S) held along the run, and the restart of the
+inverse-overlap iteration after a long nuclear step.
+
+The leapfrog step multiplies the (i, j) element of rho in the generalized
+eigenbasis by the roots of z^2 + 2 i theta z - 1, theta = dt (eps_i - eps_j),
+which leave the unit circle once |theta| > 1 (Sec. 2.3, Eq. 19); the
+library estimates the width of the spectrum of S^-1 H from below at
+creation and refuses steps with dt times that width at or above 1. Every
+failure here is forced from the host with valid inputs; every kernel runs
+its normal course.
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle as O
+import oracle.ehrenfest as OE
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _T():
+    from paper_1912_03174_amd import tddftb as T
+    return T
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def flake():
+    s = W.flake_c24h16()
+    gs = O.ground_state(s, tol=1e-13)
+    H = O.scc_hamiltonian_fast(s.H0, s.S, s.gamma, gs.dq, s.orb_offset)
+    eps = scipy.linalg.eigh(H, s.S, eigvals_only=True)
+    return s, gs, float(eps[-1] - eps[0])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_width_estimate_bounds_the_spectrum_from_below(flake, precision):
+    """The estimate never exceeds the width of the generalized spectrum of
+    the ground-state Hamiltonian (oracle eigensolver) and comes within 2%
+    of it."""
+    T = _T()
+    s, gs, width = flake
+    say(f"width estimate flake {precision}")
+    prec = T.TD_FP64 if precision == "fp64" else T.TD_SPLIT_BF16
+    p = T.Propagator(s, rho0=gs.rho, dt=0.2, precision=prec)
+    info = p.info()
+    est = info["width_estimate"]
+    say(f"estimate {est:.6f}, exact {width:.6f}")
+    assert est <= width * (1 + 1e-12)
+    assert est > 0.98 * width
+    assert abs(info["stability"] - 0.2 * est) < 1e-12
+    p.close()
+
+
+def test_leapfrog_limit_refused_before_any_step(flake):
+    """dt just above 1 / width is refused at the first step, with the state
+    untouched; dt just below it runs, and stays bounded."""
+    T = _T()
+    s, gs, width = flake
+    say("leapfrog limit flake")
+    over = T.Propagator(s, rho0=gs.rho, dt=1.02 / width)
+    over.kick(1e-3, (1.0, 0.0, 0.0))
+    before = over.rho()[0]
+    with pytest.raises(T.TdError) as e:
+        over.step(1)
+    assert e.value.status == T.TD_EUNSTABLE
+    assert "too large for the leapfrog" in str(e.value)
+    assert over.info()["step"] == 0
+    assert np.array_equal(over.rho()[0], before)
+    over.close()
+    under = T.Propagator(s, rho0=gs.rho, dt=0.97 / width)
+    under.kick(1e-3, (1.0, 0.0, 0.0))
+    under.step(400)
+    assert np.abs(under.rho()[0]).max() < 10.0
+    under.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_electron_count_drift_is_reported(flake, precision):
+    """A restored history whose previous density holds 0.1% more electrons
+    than the current one: the leapfrog carries the previous count forward
+    (Tr(rho_{n+1} S) = Tr(rho_{n-1} S)), so after one step the count has
+    moved by 1e-3 N_e, which is reported; the consistent history is not."""
+    T = _T()
+    s, gs, _ = flake
+    say(f"electron count drift flake {precision}")
+    prec = T.TD_FP64 if precision == "fp64" else T.TD_SPLIT_BF16
+    p = T.Propagator(s, rho0=gs.rho, precision=prec)
+    p.kick(1e-3, (0.0, 1.0, 0.0))
+    p.step(3)
+    cur, prev, step, _ = p.rho(with_prev=True)
+    p.set_rho(cur, prev, step)
+    p.step(2)                                    # consistent history: fine
+    cur, prev, step, _ = p.rho(with_prev=True)
+    p.set_rho(cur, prev * (1.0 + 1e-3), step)
+    with pytest.raises(T.TdError) as e:
+        p.step(1)
+    assert e.value.status == T.TD_EUNSTABLE
+    assert "electron count" in str(e.value)
+    p.close()
+
+
+def test_inverse_restarts_after_a_long_nuclear_step():
+    """Benzene expanding at 2.5 (R - R_centre) per au of time: one step moves
+    the outer atoms by 2.4 bohr, and the inverse of the previous overlap is
+    no start for the Newton-Schulz iteration (spectral radius of 1 - S X
+    about 1.1). The iteration begins again from the scaled identity. The
+    density is zero, so the nuclei move under the charges' Coulomb forces
+    alone and no electronic integration error enters (at these speeds the
+    coupling D would spoil the electron count); positions and forces match
+    the oracle's, which inverts S exactly."""
+    T = _T()
+    s = W.benzene()
+    m = W.two_centre_model(s)
+    say("inverse restart benzene")
+    vel = 2.5 * (s.positions - s.positions.mean(axis=0))
+    rho0 = np.zeros((s.n_orb, s.n_orb), dtype=np.complex128)
+    n = 3
+    e = T.Ehrenfest(s, m, velocities=vel, rho0=rho0)
+    e.step(n)
+    restarts = e.info()["inverse_restarts"]
+    say(f"inverse restarts {restarts}")
+    assert restarts >= 1
+    pos, _ = e.nuclei()
+    F = e.forces()
+    ref = OE.propagate(s, m, rho0, vel, n, 0.2)
+    assert np.abs(pos - s.positions).max() > 2.0            # the atoms did move far
+    assert np.abs(pos - ref.positions).max() < 1e-10
+    Sn, H0n = OE.model_matrices(m, ref.positions)
+    fr = OE.forces(rho0, H0n, np.linalg.inv(Sn), *OE.fd_gradients(m, ref.positions),
+                   np.zeros(s.n_orb), -np.asarray(s.q0, dtype=np.float64), ref.positions,
+                   m["hubbard_u"], None, m)
+    assert np.abs(F - fr).max() < 1e-10 * np.abs(fr).max()
+    e.close()
