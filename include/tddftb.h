@@ -264,6 +264,35 @@ TD_API td_status td_util_gemm(int32_t precision, int32_t n_slices, int32_t m, in
                               int32_t k, const double *A, const double *B, double *C,
                               char *err, int32_t errlen);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the product of
+ * td_util_gemm, C = A B in the given precision, on device pointers and
+ * the caller's stream, allocating nothing on the device or the host.
+ * A [m x k] (leading dimension lda >= k), B [k x n] (ldb >= n) and
+ * C [m x n] (ldc >= n) are row-major float64 device arrays; hip_stream is
+ * a hipStream_t (NULL: the null stream). The call only enqueues work: C is
+ * complete once the stream reaches this point, and A and B must stay
+ * unchanged until then. The result is bit for bit td_util_gemm's.
+ * Scratch (padded copies of A, B and C, and in split-bf16 the slices and
+ * their exponents) comes from one fixed device array of
+ * TD_GEMM_NOALLOC_SCRATCH_BYTES per GPU, kept until the process ends. A
+ * product needs 8 (m k + k n + m n) bytes of it in FP64 and
+ * (8 + 2 s)(m k + n k) + 8 m n in split-bf16 with s slices (sizes padded
+ * to the tiles: m, n to 128, k to 128 or 256), so up to
+ * m = n = k = 1664 in FP64 and 1280 at s = 4; a larger one returns
+ * TD_EINVAL before any device work.
+ * Every call on a GPU uses that GPU's one array: calls that overlap on one
+ * GPU (other streams, other threads) race, so order them on one stream or
+ * with events. The first call on each device resolves the array's address
+ * (hipGetSymbolAddress), so under stream capture make one call on that
+ * device beforehand. Errors: TD_EINVAL (arguments, size), TD_EHIP (HIP
+ * errors); err (if not NULL) receives a message of at most errlen bytes. */
+#define TD_GEMM_NOALLOC_SCRATCH_BYTES (64u << 20)
+TD_API td_status td_util_gemm_noalloc(int32_t precision, int32_t n_slices, int32_t m, int32_t n,
+                                      int32_t k, const double *A, int32_t lda, const double *B,
+                                      int32_t ldb, double *C, int32_t ldc, void *hip_stream,
+                                      char *err, int32_t errlen);
+
 /* ---------------------------------------------------------------- moving nuclei
  * Ehrenfest dynamics (Sec. 2.1, Eqs. 9-15; Sec. 2.3): S, H0 and gamma are
  * rebuilt every step from a two-centre model at the current positions, the

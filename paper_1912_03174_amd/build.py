@@ -12,7 +12,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtddftb.so")
 SOURCES = ["gemm_f64.hip", "gemm_split_bf16.hip", "kernels.hip", "batch_kernels.hip", "tddftb.hip",
-           "batch.hip", "spectra.hip", "ehrenfest_kernels.hip", "plus_u_kernels.hip"]
+           "batch.hip", "spectra.hip", "ehrenfest_kernels.hip", "plus_u_kernels.hip",
+           "noalloc.hip"]
 ARCH = "gfx950"
 
 

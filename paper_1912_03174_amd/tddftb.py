@@ -32,7 +32,7 @@ EXPORTED = [
     "td_batch_create", "td_batch_kick", "td_batch_step", "td_batch_get_dipole_series",
     "td_batch_get_charges", "td_batch_get_rho", "td_batch_get_info", "td_batch_last_error",
     "td_batch_destroy", "td_spectrum", "td_transient_absorption", "td_create_ehrenfest",
-    "td_get_nuclei", "td_get_energy_series",
+    "td_get_nuclei", "td_get_energy_series", "td_util_gemm_noalloc",
 ]
 TD_BATCH_NO_GRAPH, TD_BATCH_TILE_128, TD_BATCH_TILE_64 = 1, 2, 4
 TD_BATCH_BUCKETS = 8
@@ -114,6 +114,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "td_util_gemm": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp,
                                           ctypes.c_char_p, ctypes.c_int32]),
+        "td_util_gemm_noalloc": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.c_int32, ctypes.c_int32, vp,
+                                                  ctypes.c_int32, vp, ctypes.c_int32, vp,
+                                                  ctypes.c_int32, vp, ctypes.c_char_p,
+                                                  ctypes.c_int32]),
         "td_batch_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(TdSystem),
                                              ctypes.POINTER(TdOptions), ctypes.c_uint32,
                                              ctypes.POINTER(vp), ctypes.c_char_p,
@@ -506,6 +511,20 @@ def td_util_gemm(A: np.ndarray, B: np.ndarray, precision: int = TD_FP64,
     if st != TD_OK:
         raise TdError(st, err.value.decode())
     return C
+
+
+def td_util_gemm_noalloc(m: int, n: int, k: int, A_ptr: int, lda: int, B_ptr: int, ldb: int,
+                         C_ptr: int, ldc: int, precision: int = TD_FP64, n_slices: int = 4,
+                         stream: int = 0) -> None:
+    """C = A B on device pointers (integers, e.g. tensor.data_ptr()) on the
+    given stream handle, with no allocation; the caller synchronises."""
+    err = ctypes.create_string_buffer(1024)
+    st = load().td_util_gemm_noalloc(int(precision), int(n_slices), int(m), int(n), int(k),
+                                     ctypes.c_void_p(A_ptr), int(lda), ctypes.c_void_p(B_ptr),
+                                     int(ldb), ctypes.c_void_p(C_ptr), int(ldc),
+                                     ctypes.c_void_p(stream or None), err, 1024)
+    if st != TD_OK:
+        raise TdError(st, err.value.decode())
 
 
 class Propagator:

@@ -210,3 +210,25 @@ def test_missing_library_fails_loudly():
                        timeout=120)
     assert r.returncode != 0
     assert "FileNotFoundError" in r.stderr and "is not built" in r.stderr
+
+
+def test_noalloc_gemm_rejects_before_device(T):
+    """Arguments and sizes beyond the fixed scratch array are rejected before
+    any device call (the pointers are never touched)."""
+    big = 4096
+    with pytest.raises(T.TdError) as e:
+        T.td_util_gemm_noalloc(big, big, big, 1, big, 1, big, 1, big,
+                               precision=T.TD_SPLIT_BF16, n_slices=4)
+    assert e.value.status == T.TD_EINVAL and "scratch" in str(e.value)
+    with pytest.raises(T.TdError) as e:
+        T.td_util_gemm_noalloc(2048, 2048, 2048, 1, 2048, 1, 2048, 1, 2048)
+    assert e.value.status == T.TD_EINVAL and "scratch" in str(e.value)
+    for args in ((0, 8, 8, 1, 8, 1, 8, 1, 8), (8, 8, 8, 0, 8, 1, 8, 1, 8),
+                 (8, 8, 8, 1, 7, 1, 8, 1, 8), (8, 8, 8, 1, 8, 1, 7, 1, 8),
+                 (8, 8, 8, 1, 8, 1, 8, 1, 7)):
+        with pytest.raises(T.TdError) as e:
+            T.td_util_gemm_noalloc(*args)
+        assert e.value.status == T.TD_EINVAL
+    with pytest.raises(T.TdError) as e:
+        T.td_util_gemm_noalloc(8, 8, 8, 1, 8, 1, 8, 1, 8, precision=T.TD_SPLIT_BF16, n_slices=6)
+    assert e.value.status == T.TD_EINVAL
