@@ -22,7 +22,7 @@ reported precision, the product (S^-1 H)[Re rho | Im rho] (FP64: 4 n^3
 flop per launch) or its split form (issued bf16 flop per launch), timed
 with HIP events on the library's stream over the timed steps.
 `cpu_baseline` times the CPU oracle on a bounded sample of the workload.
-`probe_batch` (beside the main line, not part of it) times a batch of 64
+`probe_batch` (beside the main line, not part of it) times a batch of 512
 probe trajectories with N_orb ~ U[60, 800] against solo contexts.
 """
 from __future__ import annotations
@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--batched", type=int, default=0,
                     help="instead of the N_orb=4096 step: time a batch of this many probe "
                          "trajectories (N_orb ~ U[60, 800]) against solo runs of a sample")
-    ap.add_argument("--batch-summary", type=int, default=64,
+    ap.add_argument("--batch-summary", type=int, default=512,
                     help="also time a probe batch of this many trajectories (0 to skip) and "
                          "report it beside the main line")
     ap.add_argument("--batch-flags", type=int, default=0,
@@ -88,6 +88,11 @@ def parse():
     ap.add_argument("--ehrenfest", action="store_true",
                     help="instead of the clamped-nuclei step: time moving-nuclei steps of the "
                          "499-atom strip (N_orb=1648) under the sin^2 pump (--steps, --warmup)")
+    ap.add_argument("--ehrenfest-batch", type=int, default=0,
+                    help="instead of the clamped-nuclei step: a batch of this many moving-nuclei "
+                         "trajectories of the 499-atom strip (N_orb=1648, nuclei at 300 K, each "
+                         "member its own velocity seed) under the sin^2 pump, against solo runs "
+                         "of two of them (--steps, --warmup)")
     ap.add_argument("--plus-u", action="store_true",
                     help="instead of the main line: FP64 steps/s of the N_orb=4096 strip with the "
                          "DFTB+U (FLL) correction on the carbon p shells, against the same steps "
@@ -418,6 +423,62 @@ def ehrenfest(args):
     }), flush=True)
 
 
+def ehrenfest_batch(args):
+    """Moving nuclei in a batch: member-steps/s of N trajectories of one system."""
+    import workloads as W
+    from paper_1912_03174_amd import tddftb as T
+
+    w = W.ehrenfest_workload()
+    s = w.system
+    m = W.two_centre_model(s)
+    nm = args.ehrenfest_batch
+    vel = np.array([W.thermal_velocities(s, 300.0, seed=5000 + j) for j in range(nm)])
+    field = w.field(0, args.warmup + args.steps)
+    t0 = time.perf_counter()
+    b = T.EhrenfestBatch(s, m, nm, velocities=vel, dt=w.dt, scc_tol=1e-10)
+    init_s = time.perf_counter() - t0
+    log(f"batch of {nm} created in {init_s:.1f} s")
+    if args.warmup:
+        b.step(args.warmup, field[:args.warmup])
+    t0 = time.perf_counter()
+    b.step(args.steps, field[args.warmup:])
+    el = time.perf_counter() - t0
+    mu_last = b.dipoles(nm - 1, args.steps)
+    ee, ek = b.energy_series(0, args.steps)
+    b.close()
+    # two members alone, same steps
+    solo_s = 0.0
+    same = True
+    for j in (0, nm - 1):
+        e = T.Ehrenfest(s, m, velocities=vel[j], dt=w.dt, scc_tol=1e-10)
+        if args.warmup:
+            e.step(args.warmup, field[:args.warmup])
+        t1 = time.perf_counter()
+        mu = e.step(args.steps, field[args.warmup:])
+        solo_s += time.perf_counter() - t1
+        e.close()
+        if j == nm - 1:
+            same = bool(np.array_equal(mu, mu_last))
+    n = s.n_orb
+    rate = nm * args.steps / el
+    flop = 12.0 * n ** 3                      # S^-1 H, (S^-1 H) rho, S^-1 D, (S^-1 D) rho
+    print(json.dumps({
+        "metric": "moving-nuclei member-steps/s, batch of one system (FP64)", "value": rate,
+        "unit": "member-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name} x{nm}", "members": nm, "n_orb": n,
+                   "n_atoms": s.n_atoms, "field": "sin^2 pump 0.15 Ha, 0.01 au, 10 fs",
+                   "nuclei": "300 K, velocity seeds 5000 ..", "parallelism": "single GPU"},
+        "product_tflops": flop * rate / 1e12,
+        "fp64_peak_frac": flop * rate / 1e12 / FP64_PEAK_TFLOPS,
+        "solo_member_steps_per_s": 2 * args.steps / solo_s,
+        "speedup_vs_solo": rate / (2 * args.steps / solo_s),
+        "last_member_bitwise_equal_to_solo": same,
+        "init_s": init_s, "e_total_change_member0": float((ee[-1] + ek[-1]) - (ee[0] + ek[0])),
+    }), flush=True)
+
+
 def batched(args):
     """Probe batch: member-steps/s of one batch against solo contexts.
 
@@ -591,6 +652,9 @@ def main():
         return
     if args.plus_u:
         plus_u(args)
+        return
+    if args.ehrenfest_batch:
+        ehrenfest_batch(args)
         return
     if args.small:
         small(args)

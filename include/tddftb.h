@@ -135,10 +135,10 @@ typedef struct {
   int32_t profile;             /* 1: time kernel classes with HIP events        */
   void *hip_stream;            /* hipStream_t to use, or NULL for an own stream */
   int32_t n_slices_dh;         /* split-bf16: slices of the S^-1 dH product     */
-                               /* (3 .. n_slices), 0: n_slices. That product    */
-                               /* carries only the change of H from the         */
-                               /* reference, so its rounding enters the density */
-                               /* scaled by that change                          */
+                               /* (3 .. n_slices), 0: n_slices. For accuracy    */
+                               /* studies: that product multiplies rho_ref,     */
+                               /* so fewer slices there cost accuracy much as   */
+                               /* in the other product                           */
 } td_options;
 
 /* Statistics of the initialisation. */
@@ -408,6 +408,38 @@ TD_API td_status td_batch_get_charges(td_batch *b, int32_t member, double *dq);
 TD_API td_status td_batch_get_rho(td_batch *b, int32_t member, double *rho, double *rho_prev,
                                   int64_t *step, int32_t *has_prev);
 TD_API td_status td_batch_get_info(td_batch *b, td_batch_info *info);
+/* A batch of moving-nuclei trajectories of one system (Sec. 2.1, Eqs.
+ * 9-15; Sec. 2.3), as in an ensemble of pump trajectories that differ in
+ * their nuclear velocities: member m is the context td_create_ehrenfest
+ * would make from sys, model and velocities[m * n_atoms * 3 ..] (NULL: all
+ * at rest). The initial density is sys->rho0, or the SCC ground state
+ * solved once for all members. opt must ask for TD_FP64. td_batch_step
+ * advances every member; each step's products (S^-1 H, (S^-1 H) rho,
+ * S^-1 D, (S^-1 D) rho, and the Newton-Schulz products of the S^-1 update)
+ * run as one grouped launch over all members, the other passes per member,
+ * spread over four streams of the batch between the grouped launches, and
+ * the residual checks of the S^-1 updates of all members share one host
+ * synchronisation per round. Every member
+ * follows exactly the trajectory of its solo context (bitwise).
+ * td_batch_kick, td_batch_get_dipole_series, td_batch_get_charges,
+ * td_batch_get_rho and td_batch_destroy work on it as on a probe batch;
+ * td_batch_get_info reports the member count and step. */
+TD_API td_status td_batch_create_ehrenfest(int32_t n, const td_system *sys,
+                                           const td_model *model, const double *velocities,
+                                           const td_options *opt, td_batch **out, char *err,
+                                           int32_t errlen);
+
+/* Nuclear state of member m of a moving-nuclei batch, as td_get_nuclei;
+ * TD_ENOTSUP for a clamped-nuclei batch. */
+TD_API td_status td_batch_get_nuclei(td_batch *b, int32_t member, double *positions,
+                                     double *velocities);
+
+/* Energy series of member m of a moving-nuclei batch for the last
+ * td_batch_step, as td_get_energy_series; TD_ENOTSUP for a clamped-nuclei
+ * batch. */
+TD_API td_status td_batch_get_energy_series(td_batch *b, int32_t member, double *e_el,
+                                            double *e_kin, int32_t cap, int32_t *n_out);
+
 TD_API const char *td_batch_last_error(const td_batch *b);
 TD_API void td_batch_destroy(td_batch *b);
 

@@ -69,6 +69,9 @@ struct td_batch {
   int cap = 0;
   hipGraphExec_t graph[2] = {nullptr, nullptr};       // one leapfrog step, by parity
   hipGraphExec_t graph_run[2] = {nullptr, nullptr};   // kGraphRun steps, by parity
+  // moving nuclei: members of one system, grouped products per step phase
+  bool ehr = false;
+  tdi::EhrGroup eg;
 };
 
 namespace {
@@ -269,6 +272,7 @@ void refresh_members(td_batch* b) {
 void free_batch(td_batch* b) {
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   drop_graphs(b);
+  tdi::ehr_group_free(b->eg);
   void* bufs[] = {b->mem_d, b->rows_d, b->atoms_d, b->pairs_d, b->g1_d[0], b->g1_d[1],
                   b->g2_d[0][0], b->g2_d[0][1], b->g2_d[1][0], b->g2_d[1][1], b->field,
                   b->dip, b->kstep};
@@ -369,6 +373,33 @@ void create_impl(td_batch* b, int n, const td_system* systems, const td_options*
   HIPCHK(b, hipStreamSynchronize(b->stream));
 }
 
+void ehr_step_impl(td_batch* b, int n, const double* field) {
+  if (field) {
+    if (b->cap < n) {
+      if (b->field) HIPCHK(b, hipFree(b->field));
+      b->field = nullptr;
+      b->cap = 0;
+      HIPCHK(b, hipMalloc((void**)&b->field, sizeof(double) * 3 * (size_t)n));
+      b->cap = n;
+    }
+    HIPCHK(b, hipMemcpyAsync(b->field, field, sizeof(double) * 3 * n, hipMemcpyHostToDevice,
+                             b->stream));
+  }
+  for (int m = 0; m < b->nm; ++m) {
+    try {
+      tdi::ensure_series_ctx(b->mem[m], n);
+    } catch (const Fail&) {
+      b->err = "member " + std::to_string(m) + ": " + b->mem[m]->err;
+      throw;
+    }
+  }
+  b->last_n = 0;
+  tdi::ehr_batch_steps(b->mem, b->eg, n, field ? b->field : nullptr, b->err);
+  b->step += n;
+  b->has_prev = true;
+  b->last_n = n;
+}
+
 void step_impl(td_batch* b, int n, const double* field) {
   REQUIRE(b, n >= 0, TD_EINVAL, "n must be >= 0");
   // the leapfrog limit of each member (Sec. 2.3, Eq. 19), as a solo td_step checks it
@@ -388,6 +419,10 @@ void step_impl(td_batch* b, int n, const double* field) {
   if (field) {
     for (size_t i = 0; i < 3 * (size_t)n; ++i)
       REQUIRE(b, std::isfinite(field[i]), TD_EINVAL, "non-finite field");
+  }
+  if (b->ehr) {
+    ehr_step_impl(b, n, field);
+    return;
   }
   if (b->cap < n) {
     drop_graphs(b);   // the graphs hold the old buffers
@@ -434,7 +469,7 @@ void step_impl(td_batch* b, int n, const double* field) {
 
 void kick_impl(td_batch* b, const double* e0, const double* dir) {
   REQUIRE(b, e0 && dir, TD_EINVAL, "e0 and dir must not be null");
-  sync_members(b);
+  if (!b->ehr) sync_members(b);
   for (int m = 0; m < b->nm; ++m) {
     const td_status st = td_kick(b->mem[m], e0[m], dir + 3 * (size_t)m);
     if (st != TD_OK) {
@@ -443,7 +478,58 @@ void kick_impl(td_batch* b, const double* e0, const double* dir) {
     }
   }
   b->has_prev = false;
-  sync_members(b);
+  if (!b->ehr) sync_members(b);
+}
+
+// Members of one system with their own nuclear velocities: member 0 solves
+// the ground state (unless sys->rho0 is given), the others start from its
+// density; all run on the batch's stream.
+void create_ehr_impl(td_batch* b, int n, const td_system* sys, const td_model* model,
+                     const double* velocities, const td_options* opt) {
+  REQUIRE(b, n >= 1 && sys && model && opt, TD_EINVAL, "need n >= 1, system, model and options");
+  REQUIRE(b, opt->dt > 0 && std::isfinite(opt->dt), TD_EINVAL, "dt must be positive");
+  b->nm = n;
+  b->opt = *opt;
+  b->ehr = true;
+  b->flags = TD_BATCH_NO_GRAPH;
+  if (opt->hip_stream) {
+    b->stream = (hipStream_t)opt->hip_stream;
+  } else {
+    HIPCHK(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    b->own_stream = true;
+  }
+  td_options mo = *opt;
+  mo.hip_stream = b->stream;
+  mo.profile = 0;
+  const size_t na3 = 3 * (size_t)sys->n_atoms;
+  std::vector<double> rho0;
+  td_system s = *sys;
+  b->mem.reserve(n);
+  for (int m = 0; m < n; ++m) {
+    td_ctx* c = nullptr;
+    char msg[512];
+    const td_status st = td_create_ehrenfest(&s, model, velocities ? velocities + m * na3 : nullptr,
+                                             &mo, &c, msg, sizeof(msg));
+    if (st != TD_OK) {
+      b->err = "member " + std::to_string(m) + ": " + msg;
+      throw Fail{st};
+    }
+    b->mem.push_back(c);
+    if (m == 0 && !sys->rho0) {
+      const size_t n2 = (size_t)sys->n_orb * sys->n_orb;
+      rho0.resize(2 * n2);
+      int64_t step = 0;
+      int32_t hp = 0;
+      const td_status g = td_get_rho(c, rho0.data(), nullptr, &step, &hp);
+      if (g != TD_OK) {
+        b->err = std::string("member 0: ") + td_last_error(c);
+        throw Fail{g};
+      }
+      s.rho0 = rho0.data();
+    }
+  }
+  tdi::ehr_group_alloc(b->mem[0], b->eg, n);
+  HIPCHK(b, hipStreamSynchronize(b->stream));
 }
 
 void check_member(td_batch* b, int m) {
@@ -496,6 +582,14 @@ td_status td_batch_get_dipole_series(td_batch* b, int32_t member, double* mu, in
   return guarded(b, [&] {
     check_member(b, member);
     REQUIRE(b, n_out && cap >= 0 && (mu || cap == 0), TD_EINVAL, "invalid output");
+    if (b->ehr) {
+      const td_status st = td_get_dipole_series(b->mem[member], mu, cap, n_out);
+      if (st != TD_OK) {
+        b->err = "member " + std::to_string(member) + ": " + td_last_error(b->mem[member]);
+        throw Fail{st};
+      }
+      return;
+    }
     const int k = std::min(cap, b->last_n);
     if (k > 0)
       HIPCHK(b, hipMemcpyAsync(mu, b->dip + (size_t)member * b->cap * 3, sizeof(double) * 3 * k,
@@ -515,7 +609,7 @@ td_status td_batch_get_rho(td_batch* b, int32_t member, double* rho, double* rho
                            int64_t* step, int32_t* has_prev) {
   td_status st = guarded(b, [&] {
     check_member(b, member);
-    sync_members(b);
+    if (!b->ehr) sync_members(b);
   });
   if (st != TD_OK) return st;
   return member_call(b, member, td_get_rho(b->mem[member], rho, rho_prev, step, has_prev));
@@ -536,6 +630,50 @@ td_status td_batch_get_info(td_batch* b, td_batch_info* info) {
       info->bucket_ms[k][1] = b->bucket_ms[k][1];
     }
   });
+}
+
+td_status td_batch_create_ehrenfest(int32_t n, const td_system* sys, const td_model* model,
+                                    const double* velocities, const td_options* opt,
+                                    td_batch** out, char* err, int32_t errlen) {
+  if (!out) {
+    set_err(err, errlen, "out must not be null");
+    return TD_EINVAL;
+  }
+  *out = nullptr;
+  td_batch* b = new (std::nothrow) td_batch();
+  if (!b) {
+    set_err(err, errlen, "host allocation failed");
+    return TD_ENOMEM;
+  }
+  const td_status st = guarded(b, [&] { create_ehr_impl(b, n, sys, model, velocities, opt); });
+  if (st != TD_OK) {
+    set_err(err, errlen, b->err);
+    free_batch(b);
+    delete b;
+    return st;
+  }
+  set_err(err, errlen, "");
+  *out = b;
+  return TD_OK;
+}
+
+td_status td_batch_get_nuclei(td_batch* b, int32_t member, double* positions, double* velocities) {
+  td_status st = guarded(b, [&] {
+    check_member(b, member);
+    REQUIRE(b, b->ehr, TD_ENOTSUP, "clamped-nuclei batch: no nuclear state");
+  });
+  if (st != TD_OK) return st;
+  return member_call(b, member, td_get_nuclei(b->mem[member], positions, velocities));
+}
+
+td_status td_batch_get_energy_series(td_batch* b, int32_t member, double* e_el, double* e_kin,
+                                     int32_t cap, int32_t* n_out) {
+  td_status st = guarded(b, [&] {
+    check_member(b, member);
+    REQUIRE(b, b->ehr, TD_ENOTSUP, "clamped-nuclei batch: no energy series");
+  });
+  if (st != TD_OK) return st;
+  return member_call(b, member, td_get_energy_series(b->mem[member], e_el, e_kin, cap, n_out));
 }
 
 const char* td_batch_last_error(const td_batch* b) { return b ? b->err.c_str() : "null batch"; }

@@ -52,6 +52,10 @@ struct GemmProblem {
 // both give bitwise identical results.
 hipError_t dgemm_grouped(hipStream_t s, int tile, const GemmProblem* probs, int nprob,
                          int ntiles);
+// The second half of dgemm_symmetric for a C whose 64-wide tiles on and
+// above the diagonal are computed (upper problems of a 64-tile grouped
+// launch): the tiles below from their transposes.
+hipError_t symmetric_mirror(hipStream_t s, double* C, int ldc, int n);
 
 // ---------------------------------------------------------------- batches
 // Device buffers of one trajectory of a batch (layouts as for one

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/tddftb.h"
+#include "common.hpp"
 
 struct td_ctx {
   int na = 0, n = 0, np = 0, nelec = 0;
@@ -129,6 +130,33 @@ td_status guarded(C* ctx, F&& f) {
     return TD_EHIP;
   }
 }
+
+// Device tables of the grouped products of a batch of moving-nuclei
+// trajectories: `slots` tables of `per` problems, filled from a pinned host
+// mirror and reused after the stream has been synchronised; res_host holds
+// one Newton-Schulz residual per member.
+struct EhrGroup {
+  td::GemmProblem* dev = nullptr;
+  td::GemmProblem* host = nullptr;
+  double* res_host = nullptr;
+  int slots = 0, per = 0, used = 0;
+  // the per-member passes between two grouped launches spread over
+  // kLanes streams (default priority), joined by events
+  static constexpr int kLanes = 4;
+  hipStream_t lane[kLanes] = {};
+  hipEvent_t fork = nullptr, join[kLanes] = {};
+};
+void ehr_group_alloc(td_ctx* c, EhrGroup& g, int nm);
+void ehr_group_free(EhrGroup& g);
+// n moving-nuclei steps of every member (contexts of one system on one
+// stream): the step's products as grouped launches over all members, the
+// other passes per member, the arithmetic of one trajectory (each member
+// follows its solo trajectory bit for bit). field: device [n * 3] or null.
+// On failure err names the member.
+void ehr_batch_steps(std::vector<td_ctx*>& mem, EhrGroup& g, int nsteps, const double* field,
+                     std::string& err);
+// Device series for nsteps dipoles and energies.
+void ensure_series_ctx(td_ctx* c, int nsteps);
 
 // Waits for the context's stream.
 void sync_ctx(td_ctx* c);

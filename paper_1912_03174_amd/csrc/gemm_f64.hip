@@ -470,6 +470,12 @@ hipError_t dgemm_symmetric(hipStream_t s, int n, int k, const double* A, int lda
   return hipGetLastError();
 }
 
+hipError_t symmetric_mirror(hipStream_t s, double* C, int ldc, int n) {
+  if (n <= 0 || n % 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mirror_lower, dim3(n / 32, n / 32), dim3(256), 0, s, C, ldc);
+  return hipGetLastError();
+}
+
 hipError_t dgemm_grouped(hipStream_t s, int tile, const GemmProblem* probs, int nprob,
                          int ntiles) {
   if (nprob <= 0 || ntiles <= 0 || !probs) return hipErrorInvalidValue;

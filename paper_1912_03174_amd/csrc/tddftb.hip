@@ -166,14 +166,36 @@ void refresh(td_ctx* c, bool reference = false) {
 // before is kept too (moving nuclei), from the linear extrapolation
 // 2 X_n - X_{n-1} along the trajectory, whose residual is second order in
 // the step instead of first.
-void inverse_overlap(td_ctx* c, bool warm = false) {
-  const int n = c->n, np = c->np;
+//
+// The iteration is a sequence of decisions on the measured residual
+// max |1 - S X| (ns_decide), shared by one trajectory and by batches of
+// them: the same decisions in the same order give bitwise the same inverse.
+struct NsIter {
+  bool warm = false, restarted = false, done = false;
+  double prev = INFINITY, res = INFINITY;
+  int it = 0;
+};
+enum NsAction { NS_UPDATE, NS_RESTART, NS_DONE };
+
+// X = I / g, g the Gershgorin bound of the largest eigenvalue of S.
+void ns_cold_start(td_ctx* c) {
+  HIPCHK(c, td::gershgorin(c->stream, c->S, c->np, c->n, c->work1, c->work2,
+                           c->scal + SC_BOUNDS));
+  double b[2];
+  read_scal(c, SC_BOUNDS, b, 2);
+  REQUIRE(c, std::isfinite(b[1]) && b[1] > 0, TD_ENOTPOSDEF, "S has no positive spectrum bound");
+  HIPCHK(c, td::scaled_identity(c->stream, c->Sinv, c->np, c->n, 1.0 / b[1]));
+}
+
+// The starting inverse. Warm: from the inverses at earlier positions of the
+// trajectory, the quadratic extrapolation 3 X_n - 3 X_{n-1} + X_{n-2}
+// (residual third order in the step), linear 2 X_n - X_{n-1} while only two
+// are known, X_n itself at the first.
+void ns_begin(td_ctx* c, bool warm, NsIter& s) {
+  s = NsIter{};
+  s.warm = warm;
   if (warm && c->Sinv_prev) {
-    // Start from the inverses at earlier positions of the trajectory: the
-    // quadratic extrapolation 3 X_n - 3 X_{n-1} + X_{n-2} (residual third
-    // order in the step), linear 2 X_n - X_{n-1} while only two are known,
-    // X_n itself at the first.
-    const size_t len = (size_t)np * np;
+    const size_t len = (size_t)c->np * c->np;
     if (c->sinv_hist == 0) {
       HIPCHK(c, hipMemcpyAsync(c->Sinv_prev, c->Sinv, sizeof(double) * len,
                                hipMemcpyDeviceToDevice, c->stream));
@@ -188,54 +210,73 @@ void inverse_overlap(td_ctx* c, bool warm = false) {
     }
     c->sinv_hist = std::min(c->sinv_hist + 1, 2);
   }
-  if (!warm) {
-    HIPCHK(c, td::gershgorin(c->stream, c->S, np, n, c->work1, c->work2, c->scal + SC_BOUNDS));
-    double b[2];
-    read_scal(c, SC_BOUNDS, b, 2);
-    REQUIRE(c, std::isfinite(b[1]) && b[1] > 0, TD_ENOTPOSDEF,
-            "S has no positive spectrum bound");
-    HIPCHK(c, td::scaled_identity(c->stream, c->Sinv, np, n, 1.0 / b[1]));
+  if (!warm) ns_cold_start(c);
+}
+
+// The residual of 1 - S X with T = S X in c->A, into c->scal[SC_RES].
+void ns_residual(td_ctx* c) {
+  HIPCHK(c, td::identity_residual(c->stream, c->A, c->np, c->n, c->work1, c->scal + SC_RES));
+}
+
+// What to do with the residual just measured.
+NsAction ns_decide(td_ctx* c, NsIter& s, double res) {
+  s.it += 1;
+  s.res = res;
+  REQUIRE(c, s.it <= 200, TD_ENOTPOSDEF, "S is singular or indefinite: inverse did not converge");
+  // A warm start converges only while the spectral radius of 1 - S X is
+  // below 1, which the element-wise residual does not bound: after a long
+  // nuclear step (a start residual above 1/4) or a residual that grows,
+  // begin again from the scaled identity, which always converges.
+  if (s.warm && !s.restarted && !(res <= 0.25 && res < s.prev)) {
+    s.restarted = true;
+    s.prev = INFINITY;
+    c->info.inverse_restarts += 1;
+    return NS_RESTART;
   }
-  double prev = INFINITY, res = INFINITY;
-  bool restarted = false;
-  int it = 0;
-  for (it = 1; it <= 200; ++it) {
+  REQUIRE(c, std::isfinite(res) && res < 1e3, TD_ENOTPOSDEF,
+          "S is not positive definite: inverse iteration diverged");
+  if (res < 1e-15 || (res < 1e-9 && res >= 0.5 * s.prev)) return NS_DONE;
+  s.prev = res;
+  return NS_UPDATE;
+}
+
+// After the update X (2 - S X) (the new X in c->Sinv): the residual squares
+// with each update, so from a warm start below 1e-8 the updated inverse is
+// at the rounding floor and the iteration stops without a check.
+void ns_updated(td_ctx* c, NsIter& s) {
+  std::swap(c->Sinv, c->H);
+  c->info.inverse_updates += 1;
+  if (s.warm && s.res < 1e-8) s.done = true;
+}
+
+void ns_finish(td_ctx* c, const NsIter& s) {
+  REQUIRE(c, s.res < 1e-8, TD_ENOTPOSDEF, "S is singular or indefinite: inverse did not converge");
+  HIPCHK(c, td::pair_sym(c->stream, c->Sinv, c->np, c->Sinv, nullptr, c->np, c->np));
+  c->info.inverse_iterations = s.it;
+  c->info.inverse_residual = s.res;
+}
+
+void inverse_overlap(td_ctx* c, bool warm = false) {
+  const int np = c->np;
+  NsIter s;
+  ns_begin(c, warm, s);
+  while (!s.done) {
     gemm(c, 0, np, np, np, 1.0, c->S, np, c->Sinv, np, c->A, np);     // T = S X
-    HIPCHK(c, td::identity_residual(c->stream, c->A, np, n, c->work1, c->scal + SC_RES));
+    ns_residual(c);
+    double res;
     read_scal(c, SC_RES, &res, 1);
-    // A warm start converges only while the spectral radius of 1 - S X is
-    // below 1, which the element-wise residual does not bound: after a long
-    // nuclear step (a start residual above 1/4) or a residual that grows,
-    // begin again from the scaled identity, which always converges.
-    if (warm && !restarted && !(res <= 0.25 && res < prev)) {
-      HIPCHK(c, td::gershgorin(c->stream, c->S, np, n, c->work1, c->work2, c->scal + SC_BOUNDS));
-      double b[2];
-      read_scal(c, SC_BOUNDS, b, 2);
-      REQUIRE(c, std::isfinite(b[1]) && b[1] > 0, TD_ENOTPOSDEF,
-              "S has no positive spectrum bound");
-      HIPCHK(c, td::scaled_identity(c->stream, c->Sinv, np, n, 1.0 / b[1]));
-      restarted = true;
-      prev = INFINITY;
-      c->info.inverse_restarts += 1;
+    const NsAction a = ns_decide(c, s, res);
+    if (a == NS_RESTART) {
+      ns_cold_start(c);
       continue;
     }
-    REQUIRE(c, std::isfinite(res) && res < 1e3, TD_ENOTPOSDEF,
-            "S is not positive definite: inverse iteration diverged");
-    if (res < 1e-15 || (res < 1e-9 && res >= 0.5 * prev)) break;
-    prev = res;
-    HIPCHK(c, td::two_minus(c->stream, c->A, np, n));                   // 2 - S X
+    if (a == NS_DONE) break;
+    HIPCHK(c, td::two_minus(c->stream, c->A, np, c->n));               // 2 - S X
     // X (2 - S X) = 2 X - X S X is symmetric: the upper tiles and a mirror
     HIPCHK(c, td::dgemm_symmetric(c->stream, np, np, c->Sinv, np, c->A, np, c->H, np));
-    std::swap(c->Sinv, c->H);
-    c->info.inverse_updates += 1;
-    // The residual I - S X squares with each update: from a warm start below
-    // 1e-8 the updated inverse is at the rounding floor; stop without a check.
-    if (warm && res < 1e-8) break;
+    ns_updated(c, s);
   }
-  REQUIRE(c, res < 1e-8, TD_ENOTPOSDEF, "S is singular or indefinite: inverse did not converge");
-  HIPCHK(c, td::pair_sym(c->stream, c->Sinv, np, c->Sinv, nullptr, np, np));
-  c->info.inverse_iterations = it;
-  c->info.inverse_residual = res;
+  ns_finish(c, s);
 }
 
 // Zero-temperature density by second-order spectral projection (SP2,
@@ -893,9 +934,23 @@ void rebuild_model(td_ctx* c, bool warm) {
   inverse_overlap(c, warm);
 }
 
-// Charges (dipole -> mu), H with field E, X = (S^-1 H) rho_cur, W = sym Re X and
-// the forces F of the current state (Sec. 2.1, Eq. 15 without velocity terms).
-void ehr_forces(td_ctx* c, const double* E, double* mu, double* energy3) {
+// One moving-nuclei step (r18) in phases, shared by one trajectory and by
+// batches of them. Between the phases come the step's products: one
+// trajectory runs each on its own, a batch runs each over all its members
+// in one grouped launch, with the same arithmetic (the same MFMA sequence
+// over k for every element).
+//   phase_h:       charges (dipole -> mu), energy (-> energy3, optional),
+//                  potential with the field E, H
+//                     then A = S^-1 H and X = A rho
+//   phase_forces:  W = sym Re X and the forces (Sec. 2.1, Eq. 15 without
+//                  velocity terms)
+//   phase_nac:     v_k (velocity Verlet), kinetic energy, D from v_k
+//                     then A = S^-1 D and Z = A rho
+//   phase_move:    leapfrog with X - iZ (Sec. 2.1, Eq. 10; Sec. 2.3,
+//                  Eq. 19), v_{k+1/2}, drift, S, H0, gradients and gamma at
+//                  R_{k+1}
+//                     then the Newton-Schulz update of S^-1
+void ehr_phase_h(td_ctx* c, const double* E, double* mu, double* energy3) {
   hipStream_t st = c->stream;
   const int np = c->np, na = c->na;
   mulliken(c, mu);
@@ -906,28 +961,29 @@ void ehr_forces(td_ctx* c, const double* E, double* mu, double* energy3) {
   }
   HIPCHK(c, td::potential(st, c->gamma, c->dq, c->pos, E, c->orb_off, na, c->v, c->vorb));
   HIPCHK(c, td::assemble_h(st, c->H0, c->S, c->vorb, c->H, np));
-  gemm(c, 1, np, np, np, 1.0, c->Sinv, np, c->H, np, c->A, np);
-  gemm(c, 2, np, 2 * np, np, 1.0, c->A, np, c->rho_cur, 2 * np, c->X, 2 * np);
-  HIPCHK(c, td::pair_sym(st, c->X, 2 * np, c->W, nullptr, np, np));
-  HIPCHK(c, td::ehrenfest_forces(st, c->rho_cur, 2 * np, c->W, c->GS, c->GH, c->vorb, c->orb_off,
-                                 c->dq, c->dgamma, E, na, c->n, np, c->F));
 }
 
-// One Ehrenfest step k (model matrices current at R_k): forces, velocity
-// Verlet around the leapfrog step of rho with the coupling D (Sec. 2.1,
-// Eqs. 10, 14, 15; Sec. 2.3, Eq. 19), then the matrices at R_{k+1}.
-void ehr_step(td_ctx* c, int k, const double* E) {
+void ehr_phase_forces(td_ctx* c, const double* E) {
+  hipStream_t st = c->stream;
+  const int np = c->np;
+  HIPCHK(c, td::pair_sym(st, c->X, 2 * np, c->W, nullptr, np, np));
+  HIPCHK(c, td::ehrenfest_forces(st, c->rho_cur, 2 * np, c->W, c->GS, c->GH, c->vorb, c->orb_off,
+                                 c->dq, c->dgamma, E, c->na, c->n, np, c->F));
+}
+
+void ehr_phase_nac(td_ctx* c, int k) {
+  hipStream_t st = c->stream;
+  const int na = c->na;
+  if (c->vel_half)
+    HIPCHK(c, td::kick_nuclei(st, c->vel, c->F, c->species, c->mass, na, 0.5 * c->opt.dt));  // v_k
+  HIPCHK(c, td::kinetic_energy(st, c->vel, c->F, c->species, c->mass, na, 0.0, c->e_kin + k));
+  HIPCHK(c, td::nac_build(st, c->GS, c->vel, c->atom_of, c->n, c->np, c->Dm));
+}
+
+void ehr_phase_move(td_ctx* c) {
   hipStream_t st = c->stream;
   const int np = c->np, na = c->na;
   const double dt = c->opt.dt;
-  ehr_forces(c, E, c->dip + 3 * (size_t)k, c->e_el + 3 * (size_t)k);
-  if (c->vel_half)
-    HIPCHK(c, td::kick_nuclei(st, c->vel, c->F, c->species, c->mass, na, 0.5 * dt));  // v_k
-  HIPCHK(c, td::kinetic_energy(st, c->vel, c->F, c->species, c->mass, na, 0.0, c->e_kin + k));
-  // X += -i S^-1 D rho with D from v_k
-  HIPCHK(c, td::nac_build(st, c->GS, c->vel, c->atom_of, c->n, np, c->Dm));
-  gemm(c, 0, np, np, np, 1.0, c->Sinv, np, c->Dm, np, c->A, np);
-  gemm(c, 0, np, 2 * np, np, 1.0, c->A, np, c->rho_cur, 2 * np, c->Z, 2 * np);
   // the leapfrog pass stages X - i Z (the coupling term) as it reads X
   if (c->has_prev) {
     HIPCHK(c, td::pair_leapfrog(st, c->X, c->X + np, 2 * np, c->rho_prev, c->rho_prev + np,
@@ -943,7 +999,50 @@ void ehr_step(td_ctx* c, int k, const double* E) {
   HIPCHK(c, td::kick_nuclei(st, c->vel, c->F, c->species, c->mass, na, 0.5 * dt));  // v_{k+1/2}
   HIPCHK(c, td::drift_nuclei(st, c->pos, c->vel, na, dt));
   c->vel_half = true;
-  rebuild_model(c, true);
+  HIPCHK(c, td::model_build(st, model_args(c), c->pos, c->S, c->H0, c->GS, c->GH, np));
+  HIPCHK(c, td::gamma_build(st, c->pos, na, c->hub_u, c->gamma, c->dgamma));
+}
+
+// Charges (dipole -> mu), H with field E, X = (S^-1 H) rho_cur, W = sym Re X and
+// the forces F of the current state (Sec. 2.1, Eq. 15 without velocity terms).
+void ehr_forces(td_ctx* c, const double* E, double* mu, double* energy3) {
+  const int np = c->np;
+  ehr_phase_h(c, E, mu, energy3);
+  gemm(c, 1, np, np, np, 1.0, c->Sinv, np, c->H, np, c->A, np);
+  gemm(c, 2, np, 2 * np, np, 1.0, c->A, np, c->rho_cur, 2 * np, c->X, 2 * np);
+  ehr_phase_forces(c, E);
+}
+
+// One Ehrenfest step k (model matrices current at R_k): forces, velocity
+// Verlet around the leapfrog step of rho with the coupling D (Sec. 2.1,
+// Eqs. 10, 14, 15; Sec. 2.3, Eq. 19), then the matrices at R_{k+1}.
+void ehr_step(td_ctx* c, int k, const double* E) {
+  const int np = c->np;
+  ehr_forces(c, E, c->dip + 3 * (size_t)k, c->e_el + 3 * (size_t)k);
+  ehr_phase_nac(c, k);
+  // X += -i S^-1 D rho with D from v_k
+  gemm(c, 0, np, np, np, 1.0, c->Sinv, np, c->Dm, np, c->A, np);
+  gemm(c, 0, np, 2 * np, np, 1.0, c->A, np, c->rho_cur, 2 * np, c->Z, 2 * np);
+  ehr_phase_move(c);
+  inverse_overlap(c, true);
+}
+
+// Device series of the dipole (and, with moving nuclei, the energies) for
+// nsteps steps.
+void ensure_series(td_ctx* c, int nsteps) {
+  if (c->dip_cap >= nsteps) return;
+  if (c->dip) (void)hipFree(c->dip);
+  c->dip = nullptr;
+  c->dip_cap = 0;
+  dalloc(c, &c->dip, 3 * (size_t)nsteps);
+  if (c->ehr) {
+    if (c->e_kin) (void)hipFree(c->e_kin);
+    if (c->e_el) (void)hipFree(c->e_el);
+    c->e_kin = c->e_el = nullptr;
+    dalloc(c, &c->e_kin, (size_t)nsteps);
+    dalloc(c, &c->e_el, 3 * (size_t)nsteps);
+  }
+  c->dip_cap = nsteps;
 }
 
 void step_impl(td_ctx* c, int nsteps, const double* field) {
@@ -969,20 +1068,7 @@ void step_impl(td_ctx* c, int nsteps, const double* field) {
     dalloc(c, &c->field, 3 * (size_t)nsteps);
     c->field_cap = nsteps;
   }
-  if (c->dip_cap < nsteps) {
-    if (c->dip) (void)hipFree(c->dip);
-    c->dip = nullptr;
-    c->dip_cap = 0;
-    dalloc(c, &c->dip, 3 * (size_t)nsteps);
-    if (c->ehr) {
-      if (c->e_kin) (void)hipFree(c->e_kin);
-      if (c->e_el) (void)hipFree(c->e_el);
-      c->e_kin = c->e_el = nullptr;
-      dalloc(c, &c->e_kin, (size_t)nsteps);
-      dalloc(c, &c->e_el, 3 * (size_t)nsteps);
-    }
-    c->dip_cap = nsteps;
-  }
+  ensure_series(c, nsteps);
   if (field)
     HIPCHK(c, hipMemcpyAsync(c->field, field, sizeof(double) * 3 * nsteps, hipMemcpyHostToDevice,
                              c->stream));
@@ -1302,6 +1388,203 @@ void create_ehr_impl(td_ctx* c, const td_system* s, const td_model* m, const dou
 namespace tdi {
 void sync_ctx(td_ctx* c) { sync(c); }
 void refresh_ctx(td_ctx* c) { refresh(c); }
+
+void ehr_group_alloc(td_ctx* c, EhrGroup& g, int nm) {
+  g.per = nm;
+  g.slots = 16;
+  HIPCHK(c, hipMalloc((void**)&g.dev, sizeof(td::GemmProblem) * (size_t)g.slots * nm));
+  HIPCHK(c, hipHostMalloc((void**)&g.host, sizeof(td::GemmProblem) * (size_t)g.slots * nm,
+                          hipHostMallocDefault));
+  HIPCHK(c, hipHostMalloc((void**)&g.res_host, sizeof(double) * nm, hipHostMallocDefault));
+  HIPCHK(c, hipEventCreateWithFlags(&g.fork, hipEventDisableTiming));
+  for (int i = 0; i < EhrGroup::kLanes; ++i) {
+    HIPCHK(c, hipStreamCreateWithFlags(&g.lane[i], hipStreamNonBlocking));
+    HIPCHK(c, hipEventCreateWithFlags(&g.join[i], hipEventDisableTiming));
+  }
+}
+
+void ehr_group_free(EhrGroup& g) {
+  for (int i = 0; i < EhrGroup::kLanes; ++i) {
+    if (g.lane[i]) {
+      (void)hipStreamSynchronize(g.lane[i]);
+      (void)hipStreamDestroy(g.lane[i]);
+    }
+    if (g.join[i]) (void)hipEventDestroy(g.join[i]);
+  }
+  if (g.fork) (void)hipEventDestroy(g.fork);
+  if (g.dev) (void)hipFree(g.dev);
+  if (g.host) (void)hipHostFree(g.host);
+  if (g.res_host) (void)hipHostFree(g.res_host);
+  g = EhrGroup{};
+}
+
+namespace {
+
+// One grouped launch of the problems in `pr` through the next table slot;
+// slots are reused only after the stream has been synchronised.
+void grouped_launch(td_ctx* c0, EhrGroup& g, std::vector<td::GemmProblem>& pr, int tile) {
+  if (pr.empty()) return;
+  REQUIRE(c0, g.used < g.slots && (int)pr.size() <= g.per, TD_EHIP,
+          "internal: grouped product tables exhausted");
+  int t = 0;
+  for (auto& q : pr) {
+    q.tile0 = t;
+    t += q.upper ? q.tiles_n * (q.tiles_n + 1) / 2 : q.tiles_m * q.tiles_n;
+  }
+  td::GemmProblem* h = g.host + (size_t)g.used * g.per;
+  td::GemmProblem* d = g.dev + (size_t)g.used * g.per;
+  std::copy(pr.begin(), pr.end(), h);
+  HIPCHK(c0, hipMemcpyAsync(d, h, sizeof(td::GemmProblem) * pr.size(), hipMemcpyHostToDevice,
+                            c0->stream));
+  HIPCHK(c0, td::dgemm_grouped(c0->stream, tile, d, (int)pr.size(), t));
+  g.used += 1;
+  pr.clear();
+}
+
+td::GemmProblem problem(const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+                        int rows, int cols, int K, int tile, int upper) {
+  td::GemmProblem q{};
+  q.A = A;
+  q.B = B;
+  q.C = C;
+  q.lda = lda;
+  q.ldb = ldb;
+  q.ldc = ldc;
+  q.K = K;
+  q.tiles_m = rows / tile;
+  q.tiles_n = cols / tile;
+  q.upper = upper;
+  return q;
+}
+
+}  // namespace
+
+void ehr_batch_steps(std::vector<td_ctx*>& mem, EhrGroup& g, int nsteps, const double* field,
+                     std::string& err) {
+  const int nm = (int)mem.size();
+  td_ctx* c0 = mem[0];
+  hipStream_t st = c0->stream;
+  const int np = c0->np;
+  constexpr int T = 128;       // np is a multiple of 128; 64 and 128 tiles give the same sums
+  // The per-member passes between two grouped launches: member m runs on
+  // lane m mod kLanes (its context's stream switched for the duration), the
+  // lanes start after the work already on the batch stream and the batch
+  // stream waits for all of them. Each member's kernels keep their order.
+  auto each = [&](auto&& f) {
+    HIPCHK(c0, hipEventRecord(g.fork, st));
+    for (int i = 0; i < EhrGroup::kLanes; ++i) HIPCHK(c0, hipStreamWaitEvent(g.lane[i], g.fork, 0));
+    for (int m = 0; m < nm; ++m) {
+      td_ctx* c = mem[m];
+      c->stream = g.lane[m % EhrGroup::kLanes];
+      try {
+        f(c, m);
+      } catch (const Fail&) {
+        c->stream = st;
+        err = "member " + std::to_string(m) + ": " + c->err;
+        throw;
+      }
+      c->stream = st;
+    }
+    for (int i = 0; i < EhrGroup::kLanes; ++i) {
+      HIPCHK(c0, hipEventRecord(g.join[i], g.lane[i]));
+      HIPCHK(c0, hipStreamWaitEvent(st, g.join[i], 0));
+    }
+  };
+  std::vector<td::GemmProblem> pr;
+  std::vector<NsIter> ns(nm);
+  std::vector<char> active(nm);
+  std::vector<int> upd;
+  g.used = 0;
+  for (int k = 0; k < nsteps; ++k) {
+    const double* E = field ? field + 3 * (size_t)k : nullptr;
+    each([&](td_ctx* c, int) { ehr_phase_h(c, E, c->dip + 3 * (size_t)k, c->e_el + 3 * (size_t)k); });
+    for (td_ctx* c : mem) pr.push_back(problem(c->Sinv, np, c->H, np, c->A, np, np, np, np, T, 0));
+    grouped_launch(c0, g, pr, T);                                   // A = S^-1 H
+    for (td_ctx* c : mem)
+      pr.push_back(problem(c->A, np, c->rho_cur, 2 * np, c->X, 2 * np, np, 2 * np, np, T, 0));
+    grouped_launch(c0, g, pr, T);                                   // X = A rho
+    each([&](td_ctx* c, int) {
+      ehr_phase_forces(c, E);
+      ehr_phase_nac(c, k);
+    });
+    for (td_ctx* c : mem) pr.push_back(problem(c->Sinv, np, c->Dm, np, c->A, np, np, np, np, T, 0));
+    grouped_launch(c0, g, pr, T);                                   // A = S^-1 D
+    for (td_ctx* c : mem)
+      pr.push_back(problem(c->A, np, c->rho_cur, 2 * np, c->Z, 2 * np, np, 2 * np, np, T, 0));
+    grouped_launch(c0, g, pr, T);                                   // Z = A rho
+    each([&](td_ctx* c, int) { ehr_phase_move(c); });
+    // S^-1 at R_{k+1}: each member takes the decisions of one trajectory
+    // (ns_decide), with one host synchronisation per round for all of them
+    each([&](td_ctx* c, int m) {
+      ns_begin(c, true, ns[m]);
+      active[m] = 1;
+    });
+    for (;;) {
+      for (int m = 0; m < nm; ++m)
+        if (active[m]) {
+          td_ctx* c = mem[m];
+          pr.push_back(problem(c->S, np, c->Sinv, np, c->A, np, np, np, np, T, 0));
+        }
+      grouped_launch(c0, g, pr, T);                                 // T = S X
+      each([&](td_ctx* c, int m) {
+        if (!active[m]) return;
+        ns_residual(c);
+        HIPCHK(c, hipMemcpyAsync(g.res_host + m, c->scal + SC_RES, sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+      });
+      HIPCHK(c0, hipStreamSynchronize(st));
+      g.used = 0;
+      upd.clear();
+      each([&](td_ctx* c, int m) {
+        if (!active[m]) return;
+        const NsAction a = ns_decide(c, ns[m], g.res_host[m]);
+        if (a == NS_RESTART) {
+          ns_cold_start(c);
+        } else if (a == NS_DONE) {
+          active[m] = 0;
+        } else {
+          HIPCHK(c, td::two_minus(c->stream, c->A, np, c->n));     // 2 - S X
+          upd.push_back(m);
+        }
+      });
+      if (!upd.empty()) {
+        // X (2 - S X): the 64-wide tiles on and above the diagonal, then a mirror
+        for (int m : upd) {
+          td_ctx* c = mem[m];
+          pr.push_back(problem(c->Sinv, np, c->A, np, c->H, np, np, np, np, 64, 1));
+        }
+        grouped_launch(c0, g, pr, 64);
+        each([&](td_ctx* c, int m) {
+          if (std::find(upd.begin(), upd.end(), m) == upd.end()) return;
+          HIPCHK(c, td::symmetric_mirror(c->stream, c->H, np, np));
+          ns_updated(c, ns[m]);
+          if (ns[m].done) active[m] = 0;
+        });
+      }
+      bool any = false;
+      for (int m = 0; m < nm; ++m) any = any || active[m];
+      if (!any) break;
+    }
+    each([&](td_ctx* c, int m) {
+      ns_finish(c, ns[m]);
+      c->step += 1;
+    });
+  }
+  for (int m = 0; m < nm; ++m) {
+    td_ctx* c = mem[m];
+    try {
+      c->last_n = nsteps;
+      HIPCHK(c, hipMemcpyAsync(c->pos_h.data(), c->pos, sizeof(double) * 3 * c->na,
+                               hipMemcpyDeviceToHost, st));
+      refresh(c);
+    } catch (const Fail&) {
+      err = "member " + std::to_string(m) + ": " + c->err;
+      throw;
+    }
+  }
+}
+
+void ensure_series_ctx(td_ctx* c, int nsteps) { ensure_series(c, nsteps); }
 }  // namespace tdi
 
 extern "C" {

@@ -14,7 +14,9 @@ from typing import Optional
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libtddftb.so")
+# TDDFTB_LIB selects another build of the same library (the host-sanitized one
+# of the C ABI tests); the default is the in-tree build
+LIB_PATH = os.environ.get("TDDFTB_LIB") or os.path.join(PKG, "libtddftb.so")
 
 TD_OK, TD_EINVAL, TD_ENOMEM, TD_EHIP, TD_ENOTPOSDEF = 0, -1, -2, -3, -4
 TD_ESCF, TD_EUNSTABLE, TD_ENOTSUP, TD_ESTATE = -5, -6, -7, -8
@@ -33,6 +35,7 @@ EXPORTED = [
     "td_batch_get_charges", "td_batch_get_rho", "td_batch_get_info", "td_batch_last_error",
     "td_batch_destroy", "td_spectrum", "td_transient_absorption", "td_create_ehrenfest",
     "td_get_nuclei", "td_get_energy_series", "td_util_gemm_noalloc",
+    "td_batch_create_ehrenfest", "td_batch_get_nuclei", "td_batch_get_energy_series",
 ]
 TD_BATCH_NO_GRAPH, TD_BATCH_TILE_128, TD_BATCH_TILE_64 = 1, 2, 4
 TD_BATCH_BUCKETS = 8
@@ -132,6 +135,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                               ctypes.POINTER(ctypes.c_int64), _ip]),
         "td_batch_get_info": (ctypes.c_int32, [vp, ctypes.POINTER(TdBatchInfo)]),
         "td_batch_last_error": (ctypes.c_char_p, [vp]),
+        "td_batch_create_ehrenfest": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(TdSystem),
+                                                       ctypes.POINTER(TdModel), _dp,
+                                                       ctypes.POINTER(TdOptions),
+                                                       ctypes.POINTER(vp), ctypes.c_char_p,
+                                                       ctypes.c_int32]),
+        "td_batch_get_nuclei": (ctypes.c_int32, [vp, ctypes.c_int32, _dp, _dp]),
+        "td_batch_get_energy_series": (ctypes.c_int32, [vp, ctypes.c_int32, _dp, _dp,
+                                                        ctypes.c_int32, _ip]),
         "td_batch_destroy": (None, [vp]),
         "td_create_ehrenfest": (ctypes.c_int32, [ctypes.POINTER(TdSystem), ctypes.POINTER(TdModel),
                                                  _dp, ctypes.POINTER(TdOptions),
@@ -286,11 +297,8 @@ def td_create(system, options: Optional[TdOptions] = None, rho0: Optional[np.nda
     return _create(_host_system(system, rho0, occ, plus_u), options)
 
 
-def td_create_ehrenfest(system, model: dict, velocities=None, options: Optional[TdOptions] = None,
-                        rho0: Optional[np.ndarray] = None, plus_u=None):
-    """td_create_ehrenfest over host arrays; ``model`` as workloads.two_centre_model."""
-    hs = _host_system(system, rho0, None, plus_u)
-    keep = _Keep()
+def _model_struct(model: dict, keep):
+    """TdModel over host arrays held by ``keep``."""
     keep.species = np.ascontiguousarray(model["species"], dtype=np.int32)
     keep.norb = np.ascontiguousarray(model["species_norb"], dtype=np.int32)
     keep.sk_s = _f64(model["sk_s"])
@@ -299,12 +307,20 @@ def td_create_ehrenfest(system, model: dict, velocities=None, options: Optional[
     keep.scale_h = _f64(model["scale_h"])
     keep.onsite = _f64(model["onsite"])
     keep.mass = _f64(model["mass"])
+    return TdModel(n_species=len(keep.norb), species=_ptr(keep.species, np.int32),
+                   species_norb=_ptr(keep.norb, np.int32), sk_s=_ptr(keep.sk_s),
+                   sk_h=_ptr(keep.sk_h), decay=float(model["decay"]), scale_s=_ptr(keep.scale_s),
+                   scale_h=_ptr(keep.scale_h), onsite=_ptr(keep.onsite),
+                   hubbard_u=float(model["hubbard_u"]), mass=_ptr(keep.mass))
+
+
+def td_create_ehrenfest(system, model: dict, velocities=None, options: Optional[TdOptions] = None,
+                        rho0: Optional[np.ndarray] = None, plus_u=None):
+    """td_create_ehrenfest over host arrays; ``model`` as workloads.two_centre_model."""
+    hs = _host_system(system, rho0, None, plus_u)
+    keep = _Keep()
+    m = _model_struct(model, keep)
     keep.vel = None if velocities is None else _f64(velocities)
-    m = TdModel(n_species=len(keep.norb), species=_ptr(keep.species, np.int32),
-                species_norb=_ptr(keep.norb, np.int32), sk_s=_ptr(keep.sk_s),
-                sk_h=_ptr(keep.sk_h), decay=float(model["decay"]), scale_s=_ptr(keep.scale_s),
-                scale_h=_ptr(keep.scale_h), onsite=_ptr(keep.onsite),
-                hubbard_u=float(model["hubbard_u"]), mass=_ptr(keep.mass))
     opt = options if options is not None else td_default_options()
     ctx = ctypes.c_void_p()
     err = ctypes.create_string_buffer(1024)
@@ -327,6 +343,48 @@ def td_get_energy_series(ctx, cap: int):
     ek = np.empty(max(cap, 1))
     n = ctypes.c_int32()
     _check(ctx, load().td_get_energy_series(ctx, _ptr(ee), _ptr(ek), int(cap), ctypes.byref(n)))
+    k = min(cap, n.value)
+    return ee[:k], ek[:k]
+
+
+def td_batch_create_ehrenfest(system, model: dict, n: int, velocities=None,
+                              options: Optional[TdOptions] = None,
+                              rho0: Optional[np.ndarray] = None):
+    """td_batch_create_ehrenfest: n members of one system; velocities None or
+    [n, n_atoms, 3]."""
+    hs = _host_system(system, rho0, None, None)
+    keep = _Keep()
+    m = _model_struct(model, keep)
+    if velocities is not None:
+        keep.vel = _f64(velocities).reshape(-1)
+        if keep.vel.size != n * 3 * len(system.q0):
+            raise ValueError("velocities must have shape [n, n_atoms, 3]")
+    else:
+        keep.vel = None
+    opt = options if options is not None else td_default_options()
+    b = ctypes.c_void_p()
+    err = ctypes.create_string_buffer(1024)
+    st = load().td_batch_create_ehrenfest(int(n), ctypes.byref(hs), ctypes.byref(m),
+                                          _ptr(keep.vel), ctypes.byref(opt), ctypes.byref(b),
+                                          err, 1024)
+    if st != TD_OK:
+        raise TdError(st, err.value.decode())
+    return b
+
+
+def td_batch_get_nuclei(b, member: int, n_atoms: int):
+    pos = np.empty((n_atoms, 3))
+    vel = np.empty((n_atoms, 3))
+    _bcheck(b, load().td_batch_get_nuclei(b, int(member), _ptr(pos), _ptr(vel)))
+    return pos, vel
+
+
+def td_batch_get_energy_series(b, member: int, cap: int):
+    ee = np.empty(max(cap, 1))
+    ek = np.empty(max(cap, 1))
+    n = ctypes.c_int32()
+    _bcheck(b, load().td_batch_get_energy_series(b, int(member), _ptr(ee), _ptr(ek), int(cap),
+                                                 ctypes.byref(n)))
     k = min(cap, n.value)
     return ee[:k], ek[:k]
 
@@ -669,6 +727,26 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class EhrenfestBatch(Batch):
+    """Convenience wrapper owning a batch of moving-nuclei trajectories of one system."""
+
+    def __init__(self, system, model, n, velocities=None, dt=0.2, rho0=None, scc_tol=1e-12,
+                 scc_maxiter=300):
+        opt = td_default_options()
+        opt.dt = dt
+        opt.scc_tol = scc_tol
+        opt.scc_maxiter = scc_maxiter
+        self.n_atoms = [len(system.q0)] * n
+        self.n_orb = [int(system.orb_offset[-1])] * n
+        self.b = td_batch_create_ehrenfest(system, model, n, velocities, opt, rho0)
+
+    def nuclei(self, member):
+        return td_batch_get_nuclei(self.b, member, self.n_atoms[member])
+
+    def energy_series(self, member, n):
+        return td_batch_get_energy_series(self.b, member, n)
 
 
 class Ehrenfest(Propagator):
