@@ -387,7 +387,9 @@ def plus_u(args):
 
 
 def ehrenfest(args):
-    """Moving nuclei: steps/s of the pump run on the 499-atom strip."""
+    """Moving nuclei: steps/s of the pump run on the 499-atom strip, FP64 and
+    (unless --precision fp64) split-bf16 products with rho from the same
+    start, with the split run's dipole error against FP64 over its steps."""
     import workloads as W
     from paper_1912_03174_amd import tddftb as T
 
@@ -395,31 +397,48 @@ def ehrenfest(args):
     s = w.system
     m = W.two_centre_model(s)
     vel = W.thermal_velocities(s, 300.0, seed=5000)
-    t0 = time.perf_counter()
-    e = T.Ehrenfest(s, m, velocities=vel, dt=w.dt, scc_tol=1e-10)
-    init_s = time.perf_counter() - t0
     field = w.field(0, args.warmup + args.steps)
-    if args.warmup:
-        e.step(args.warmup, field[:args.warmup])
-    upd0 = e.info()["inverse_updates"]
-    t0 = time.perf_counter()
-    e.step(args.steps, field[args.warmup:])
-    el = time.perf_counter() - t0
-    info = e.info()
-    ee, ek = e.energy_series(args.steps)
-    e.close()
     n = s.n_orb
+    runs = {}
+    precs = {"both": ("fp64", "split"), "fp64": ("fp64",), "split": ("split",)}[args.precision]
+    for name in precs:
+        prec = T.TD_FP64 if name == "fp64" else T.TD_SPLIT_BF16
+        t0 = time.perf_counter()
+        e = T.Ehrenfest(s, m, velocities=vel, dt=w.dt, scc_tol=1e-10, precision=prec,
+                        n_slices=args.slices)
+        init_s = time.perf_counter() - t0
+        mus = []
+        if args.warmup:
+            mus.append(e.step(args.warmup, field[:args.warmup]))
+        upd0 = e.info()["inverse_updates"]
+        t0 = time.perf_counter()
+        mus.append(e.step(args.steps, field[args.warmup:]))
+        el = time.perf_counter() - t0
+        info = e.info()
+        ee, ek = e.energy_series(args.steps)
+        e.close()
+        runs[name] = {
+            "steps_per_s": args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+            "trajectory_fs_per_s": args.steps / el * w.dt / W.FS,
+            "product_tflops": 12.0 * n ** 3 * args.steps / el / 1e12,
+            "init_s": init_s, "e_kin_start": float(ek[0]), "e_kin_end": float(ek[-1]),
+            "e_total_change": float((ee[-1] + ek[-1]) - (ee[0] + ek[0])),
+            "inverse_updates_per_step": (info["inverse_updates"] - upd0) / args.steps,
+            "inverse_residual_last": info["inverse_residual"],
+            "dipoles": np.concatenate(mus)}
+    if "fp64" in runs and "split" in runs:
+        ref = runs["fp64"]["dipoles"]
+        runs["split"]["dipole_rel_err_vs_fp64"] = float(
+            np.abs(runs["split"]["dipoles"] - ref).max() / np.abs(ref - ref[0]).max())
+    first = runs[precs[0]]
     print(json.dumps({
-        "metric": "moving-nuclei steps/s (FP64)", "value": args.steps / el, "unit": "steps/s",
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
+        "metric": "moving-nuclei steps/s", "value": first["steps_per_s"], "unit": "steps/s",
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": first["ms_per_step"],
+        "dtype": "f64" if precs[0] == "fp64" else "bf16",
         "config": {"workload": w.name, "n_orb": n, "n_atoms": s.n_atoms,
                    "field": "sin^2 pump 0.15 Ha, 0.01 au, 10 fs", "nuclei": "300 K"},
-        "trajectory_fs_per_s": args.steps / el * w.dt / W.FS,
-        "product_tflops": 12.0 * n ** 3 * args.steps / el / 1e12,
-        "init_s": init_s, "e_kin_start": float(ek[0]), "e_kin_end": float(ek[-1]),
-        "e_total_change": float((ee[-1] + ek[-1]) - (ee[0] + ek[0])),
-        "inverse_updates_per_step": (info["inverse_updates"] - upd0) / args.steps,
-        "inverse_residual_last": info["inverse_residual"],
+        "precisions": {k: {kk: vv for kk, vv in v.items() if kk != "dipoles"}
+                       for k, v in runs.items()},
     }), flush=True)
 
 
@@ -434,8 +453,11 @@ def ehrenfest_batch(args):
     nm = args.ehrenfest_batch
     vel = np.array([W.thermal_velocities(s, 300.0, seed=5000 + j) for j in range(nm)])
     field = w.field(0, args.warmup + args.steps)
+    split = args.precision == "split"
+    prec = T.TD_SPLIT_BF16 if split else T.TD_FP64
     t0 = time.perf_counter()
-    b = T.EhrenfestBatch(s, m, nm, velocities=vel, dt=w.dt, scc_tol=1e-10)
+    b = T.EhrenfestBatch(s, m, nm, velocities=vel, dt=w.dt, scc_tol=1e-10, precision=prec,
+                         n_slices=args.slices)
     init_s = time.perf_counter() - t0
     log(f"batch of {nm} created in {init_s:.1f} s")
     if args.warmup:
@@ -450,7 +472,8 @@ def ehrenfest_batch(args):
     solo_s = 0.0
     same = True
     for j in (0, nm - 1):
-        e = T.Ehrenfest(s, m, velocities=vel[j], dt=w.dt, scc_tol=1e-10)
+        e = T.Ehrenfest(s, m, velocities=vel[j], dt=w.dt, scc_tol=1e-10, precision=prec,
+                        n_slices=args.slices)
         if args.warmup:
             e.step(args.warmup, field[:args.warmup])
         t1 = time.perf_counter()
@@ -463,10 +486,10 @@ def ehrenfest_batch(args):
     rate = nm * args.steps / el
     flop = 12.0 * n ** 3                      # S^-1 H, (S^-1 H) rho, S^-1 D, (S^-1 D) rho
     print(json.dumps({
-        "metric": "moving-nuclei member-steps/s, batch of one system (FP64)", "value": rate,
+        "metric": "moving-nuclei member-steps/s, batch of one system", "value": rate,
         "unit": "member-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "dtype": "f64",
-        "data": "synthetic",
+        "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True,
+        "dtype": "bf16" if split else "f64", "data": "synthetic",
         "config": {"workload": f"{w.name} x{nm}", "members": nm, "n_orb": n,
                    "n_atoms": s.n_atoms, "field": "sin^2 pump 0.15 Ha, 0.01 au, 10 fs",
                    "nuclei": "300 K, velocity seeds 5000 ..", "parallelism": "single GPU"},

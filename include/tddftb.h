@@ -332,8 +332,12 @@ typedef struct {
 /* Creates a context with moving nuclei. sys gives positions, orb_offset,
  * q0, the occupations and optionally rho0 as for td_create; its S, H0 and
  * gamma are ignored (built from the model, on the GPU). velocities
- * [n_atoms * 3] bohr per au of time (NULL: at rest). FP64 precision and
- * no plus_u (TD_ENOTSUP otherwise). td_step then advances electrons and nuclei with
+ * [n_atoms * 3] bohr per au of time (NULL: at rest). No plus_u
+ * (TD_ENOTSUP). In TD_SPLIT_BF16 precision the two products with the
+ * density, (S^-1 H) rho and (S^-1 D) rho, run as split-bf16 products of
+ * rho itself (S, H0 and S^-1 change every step, so there is no fixed
+ * reference); S^-1 H, S^-1 D, the S^-1 update, charges, forces and
+ * energies stay FP64. td_step then advances electrons and nuclei with
  * the same dt; td_kick, td_get_rho / td_set_rho act on the electrons and
  * keep the nuclei. */
 TD_API td_status td_create_ehrenfest(const td_system *sys, const td_model *model,
@@ -408,15 +412,17 @@ TD_API td_status td_batch_get_charges(td_batch *b, int32_t member, double *dq);
 TD_API td_status td_batch_get_rho(td_batch *b, int32_t member, double *rho, double *rho_prev,
                                   int64_t *step, int32_t *has_prev);
 TD_API td_status td_batch_get_info(td_batch *b, td_batch_info *info);
+
 /* A batch of moving-nuclei trajectories of one system (Sec. 2.1, Eqs.
  * 9-15; Sec. 2.3), as in an ensemble of pump trajectories that differ in
  * their nuclear velocities: member m is the context td_create_ehrenfest
  * would make from sys, model and velocities[m * n_atoms * 3 ..] (NULL: all
  * at rest). The initial density is sys->rho0, or the SCC ground state
- * solved once for all members. opt must ask for TD_FP64. td_batch_step
- * advances every member; each step's products (S^-1 H, (S^-1 H) rho,
- * S^-1 D, (S^-1 D) rho, and the Newton-Schulz products of the S^-1 update)
- * run as one grouped launch over all members, the other passes per member,
+ * solved once for all members. td_batch_step advances every member; each
+ * step's FP64 products (S^-1 H, (S^-1 H) rho, S^-1 D, (S^-1 D) rho, and the
+ * Newton-Schulz products of the S^-1 update) run as one grouped launch over
+ * all members (in TD_SPLIT_BF16 precision the two products with rho run per
+ * member as split-bf16 products, as in a solo context), the other passes per member,
  * spread over four streams of the batch between the grouped launches, and
  * the residual checks of the S^-1 updates of all members share one host
  * synchronisation per round. Every member

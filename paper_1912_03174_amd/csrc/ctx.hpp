@@ -62,6 +62,10 @@ struct td_ctx {
   int *e_sinv = nullptr, *e_dh = nullptr, *e_L2 = nullptr, *e_R2 = nullptr;
   // moving nuclei (Ehrenfest); positions live in pos (device) and pos_h
   bool ehr = false;
+  bool ehr_setup = false;      // td_create_ehrenfest is building this context
+  bool ehr_split = false;      // the products with rho as split-bf16 (no reference
+                               // form: sl_L2 holds the left operand, sl_R2 the rows
+                               // of Re rho and -Im rho)
   bool vel_half = false;       // vel holds v_{n-1/2} (else v_n, before the first step)
   int nsp = 0;
   double decay = 0.0, hub_u = 0.0;

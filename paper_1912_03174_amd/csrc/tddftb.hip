@@ -898,7 +898,7 @@ void create_impl(td_ctx* c, const td_system* s_in, const td_options* o) {
   }
   refresh(c, true);                        // charges of the initial state
   spectral_width(c);
-  if (want_split) {
+  if (want_split && !c->ehr_setup) {
     split_init(c);
     c->split = true;
   }
@@ -950,6 +950,47 @@ void rebuild_model(td_ctx* c, bool warm) {
 //                  Eq. 19), v_{k+1/2}, drift, S, H0, gradients and gamma at
 //                  R_{k+1}
 //                     then the Newton-Schulz update of S^-1
+// out = A [Re rho | Im rho] (np x 2np) as a split-bf16 product, for moving
+// nuclei: there is no fixed reference (S, H0 and S^-1 change every step),
+// so rho itself is sliced. rho is Hermitian, so the rows of Re rho and of
+// -Im rho are the columns of the two halves of the right operand. With
+// `slice_rho` false the slices of rho from the previous call are reused
+// (rho unchanged in between).
+void ehr_split_product(td_ctx* c, const double* A, double* out, bool slice_rho) {
+  const int np = c->np, S = c->ns;
+  if (slice_rho) {
+    td::SliceSrc re;
+    re.M0 = c->rho_cur;
+    re.ld0 = 2 * np;
+    slice(c, td::SLICE_PLAIN, re, np, np, c->sl_R2, np * S, c->e_R2);
+    td::SliceSrc im;
+    im.M0 = c->rho_cur + np;
+    im.ld0 = 2 * np;
+    im.sign = -1.0;
+    slice(c, td::SLICE_PLAIN, im, np, np, c->sl_R2 + (size_t)np * np * S, np * S, c->e_R2 + np);
+  }
+  td::SliceSrc a;
+  a.M0 = A;
+  a.ld0 = np;
+  slice(c, td::SLICE_PLAIN, a, np, np, c->sl_L2, np * S, c->e_L2);
+  td::SplitGemm g;
+  g.m = np;
+  g.n = 2 * np;
+  g.L = c->sl_L2;
+  g.ldl = np * S;
+  g.eL = c->e_L2;
+  g.R = c->sl_R2;
+  g.ldr = np * S;
+  g.fR = c->e_R2;
+  g.seg_len = np;
+  g.k_lo = np;
+  g.k_hi = np;
+  g.n_split = 2 * np;
+  g.C = out;
+  g.ldc = 2 * np;
+  HIPCHK(c, td::split_gemm(c->stream, S, g));
+}
+
 void ehr_phase_h(td_ctx* c, const double* E, double* mu, double* energy3) {
   hipStream_t st = c->stream;
   const int np = c->np, na = c->na;
@@ -1009,7 +1050,10 @@ void ehr_forces(td_ctx* c, const double* E, double* mu, double* energy3) {
   const int np = c->np;
   ehr_phase_h(c, E, mu, energy3);
   gemm(c, 1, np, np, np, 1.0, c->Sinv, np, c->H, np, c->A, np);
-  gemm(c, 2, np, 2 * np, np, 1.0, c->A, np, c->rho_cur, 2 * np, c->X, 2 * np);
+  if (c->ehr_split)
+    ehr_split_product(c, c->A, c->X, true);
+  else
+    gemm(c, 2, np, 2 * np, np, 1.0, c->A, np, c->rho_cur, 2 * np, c->X, 2 * np);
   ehr_phase_forces(c, E);
 }
 
@@ -1022,7 +1066,10 @@ void ehr_step(td_ctx* c, int k, const double* E) {
   ehr_phase_nac(c, k);
   // X += -i S^-1 D rho with D from v_k
   gemm(c, 0, np, np, np, 1.0, c->Sinv, np, c->Dm, np, c->A, np);
-  gemm(c, 0, np, 2 * np, np, 1.0, c->A, np, c->rho_cur, 2 * np, c->Z, 2 * np);
+  if (c->ehr_split)
+    ehr_split_product(c, c->A, c->Z, false);
+  else
+    gemm(c, 0, np, 2 * np, np, 1.0, c->A, np, c->rho_cur, 2 * np, c->Z, 2 * np);
   ehr_phase_move(c);
   inverse_overlap(c, true);
 }
@@ -1312,7 +1359,10 @@ void create_ehr_impl(td_ctx* c, const td_system* s, const td_model* m, const dou
   REQUIRE(c, s && (s->flags & TD_DEVICE_PTRS) == 0, TD_EINVAL,
           "moving-nuclei contexts take host pointers");
   validate_model(c, s, m);
-  REQUIRE(c, o->precision == TD_FP64, TD_ENOTSUP, "moving nuclei run in TD_FP64 precision only");
+  REQUIRE(c, o->precision == TD_FP64 || o->precision == TD_SPLIT_BF16, TD_EINVAL,
+          "unknown precision");
+  REQUIRE(c, o->precision == TD_FP64 || (o->n_slices >= 3 && o->n_slices <= 5), TD_EINVAL,
+          "n_slices must be 3, 4 or 5");
   REQUIRE(c, s->plus_u == TD_PLUS_U_NONE, TD_ENOTSUP,
           "moving nuclei have no on-site corrections (plus_u)");
   if (vel) REQUIRE(c, finite_all(vel, 3 * (size_t)s->n_atoms), TD_EINVAL, "non-finite velocities");
@@ -1367,9 +1417,17 @@ void create_ehr_impl(td_ctx* c, const td_system* s, const td_model* m, const dou
   view.S = hS.data();
   view.H0 = hH.data();
   view.gamma = hG.data();
+  c->ehr_setup = true;                     // split precision: no reference form
   create_impl(c, &view, o);
   upload_model(c, s, m, vel);
   const size_t m2 = (size_t)c->np * c->np;
+  if (o->precision == TD_SPLIT_BF16) {
+    salloc(c, &c->sl_L2, (size_t)c->ns * m2);
+    salloc(c, &c->sl_R2, (size_t)c->ns * 2 * m2);
+    ialloc(c, &c->e_L2, c->np);
+    ialloc(c, &c->e_R2, 2 * (size_t)c->np);
+    c->ehr_split = true;
+  }
   dalloc(c, &c->W, m2);
   dalloc(c, &c->Dm, m2);
   dalloc(c, &c->Sinv_prev, m2);
@@ -1500,18 +1558,26 @@ void ehr_batch_steps(std::vector<td_ctx*>& mem, EhrGroup& g, int nsteps, const d
     each([&](td_ctx* c, int) { ehr_phase_h(c, E, c->dip + 3 * (size_t)k, c->e_el + 3 * (size_t)k); });
     for (td_ctx* c : mem) pr.push_back(problem(c->Sinv, np, c->H, np, c->A, np, np, np, np, T, 0));
     grouped_launch(c0, g, pr, T);                                   // A = S^-1 H
-    for (td_ctx* c : mem)
-      pr.push_back(problem(c->A, np, c->rho_cur, 2 * np, c->X, 2 * np, np, 2 * np, np, T, 0));
-    grouped_launch(c0, g, pr, T);                                   // X = A rho
+    if (c0->ehr_split) {
+      each([&](td_ctx* c, int) { ehr_split_product(c, c->A, c->X, true); });
+    } else {
+      for (td_ctx* c : mem)
+        pr.push_back(problem(c->A, np, c->rho_cur, 2 * np, c->X, 2 * np, np, 2 * np, np, T, 0));
+      grouped_launch(c0, g, pr, T);                                 // X = A rho
+    }
     each([&](td_ctx* c, int) {
       ehr_phase_forces(c, E);
       ehr_phase_nac(c, k);
     });
     for (td_ctx* c : mem) pr.push_back(problem(c->Sinv, np, c->Dm, np, c->A, np, np, np, np, T, 0));
     grouped_launch(c0, g, pr, T);                                   // A = S^-1 D
-    for (td_ctx* c : mem)
-      pr.push_back(problem(c->A, np, c->rho_cur, 2 * np, c->Z, 2 * np, np, 2 * np, np, T, 0));
-    grouped_launch(c0, g, pr, T);                                   // Z = A rho
+    if (c0->ehr_split) {
+      each([&](td_ctx* c, int) { ehr_split_product(c, c->A, c->Z, false); });
+    } else {
+      for (td_ctx* c : mem)
+        pr.push_back(problem(c->A, np, c->rho_cur, 2 * np, c->Z, 2 * np, np, 2 * np, np, T, 0));
+      grouped_launch(c0, g, pr, T);                                 // Z = A rho
+    }
     each([&](td_ctx* c, int) { ehr_phase_move(c); });
     // S^-1 at R_{k+1}: each member takes the decisions of one trajectory
     // (ns_decide), with one host synchronisation per round for all of them

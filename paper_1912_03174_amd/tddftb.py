@@ -733,11 +733,13 @@ class EhrenfestBatch(Batch):
     """Convenience wrapper owning a batch of moving-nuclei trajectories of one system."""
 
     def __init__(self, system, model, n, velocities=None, dt=0.2, rho0=None, scc_tol=1e-12,
-                 scc_maxiter=300):
+                 scc_maxiter=300, precision=TD_FP64, n_slices=4):
         opt = td_default_options()
         opt.dt = dt
         opt.scc_tol = scc_tol
         opt.scc_maxiter = scc_maxiter
+        opt.precision = precision
+        opt.n_slices = n_slices
         self.n_atoms = [len(system.q0)] * n
         self.n_orb = [int(system.orb_offset[-1])] * n
         self.b = td_batch_create_ehrenfest(system, model, n, velocities, opt, rho0)
@@ -753,11 +755,13 @@ class Ehrenfest(Propagator):
     """One trajectory with moving nuclei (td_create_ehrenfest)."""
 
     def __init__(self, system, model, velocities=None, dt=0.2, rho0=None, scc_tol=1e-12,
-                 scc_maxiter=300):
+                 scc_maxiter=300, precision=TD_FP64, n_slices=4):
         opt = td_default_options()
         opt.dt = dt
         opt.scc_tol = scc_tol
         opt.scc_maxiter = scc_maxiter
+        opt.precision = precision
+        opt.n_slices = n_slices
         self.n_atoms = len(system.q0)
         self.n_orb = int(system.orb_offset[-1])
         self.ctx = td_create_ehrenfest(system, model, velocities, opt, rho0=rho0)

@@ -147,9 +147,14 @@ def test_ehrenfest_arguments_rejected_before_device(T):
     m = W.two_centre_model(s)
     o = T.td_default_options()
     o.precision = T.TD_SPLIT_BF16
+    o.n_slices = 7
     with pytest.raises(T.TdError) as e:
         T.td_create_ehrenfest(s, m, None, o)
-    assert e.value.status == T.TD_ENOTSUP
+    assert e.value.status == T.TD_EINVAL
+    o.precision = 9
+    with pytest.raises(T.TdError) as e:
+        T.td_create_ehrenfest(s, m, None, o)
+    assert e.value.status == T.TD_EINVAL
     with pytest.raises(T.TdError) as e:
         T.td_create_ehrenfest(s, dict(m, decay=-1.0))
     assert e.value.status == T.TD_EINVAL

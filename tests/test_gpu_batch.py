@@ -103,12 +103,15 @@ def pump_excited(s, amount=0.1):
     return gs.rho + amount * (np.outer(cL, cL) - np.outer(cH, cH))
 
 
-def test_pump_excited_batch_matches_oracle():
+@pytest.mark.parametrize("n_lo,n_hi,seed,n", [(60, 200, 4300, 200), (600, 808, 4301, 40)])
+def test_pump_excited_batch_matches_oracle(n_lo, n_hi, seed, n):
+    """Members drawn from the small and from the large end of the probe
+    sizes (several 64- and 128-wide product tiles each), each against the
+    oracle directly."""
     T = _T()
-    systems, axes = W.probe_batch(3, seed=4300, n_lo=60, n_hi=200)
+    systems, axes = W.probe_batch(3, seed=seed, n_lo=n_lo, n_hi=n_hi)
     say(f"pump-excited batch vs oracle, sizes {[s.n_orb for s in systems]}")
     rho0 = [pump_excited(s) for s in systems]
-    n = 200
     b = T.Batch(systems, rho0s=rho0)
     b.kick(np.full(3, 1e-3), axes)
     b.step(n)

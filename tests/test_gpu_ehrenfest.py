@@ -171,9 +171,10 @@ def test_ehrenfest_errors():
     m = W.two_centre_model(s)
     o = T.td_default_options()
     o.precision = T.TD_SPLIT_BF16
+    o.n_slices = 6
     with pytest.raises(T.TdError) as err:
         T.td_create_ehrenfest(s, m, None, o)
-    assert err.value.status == T.TD_ENOTSUP
+    assert err.value.status == T.TD_EINVAL
     bad = dict(m, species_norb=np.array([4, 4], dtype=np.int32))
     with pytest.raises(T.TdError) as err:
         T.td_create_ehrenfest(s, bad)
@@ -183,3 +184,29 @@ def test_ehrenfest_errors():
         T.td_get_nuclei(p.ctx, s.n_atoms)
     assert err.value.status == T.TD_ENOTSUP
     p.close()
+
+
+@pytest.mark.parametrize("which,n", [("benzene", 150), ("strip276", 30)])
+def test_split_products_match_oracle(which, n):
+    """Split-bf16 products of rho itself for moving nuclei: the FP64 oracle's
+    trajectory (kick, laser, thermal nuclei) within the split form's
+    admissible 1e-6 of the dipole's change."""
+    T = _T()
+    s = W.benzene() if which == "benzene" else W.small_strip(8, 4, seed=1)
+    m = W.two_centre_model(s)
+    say(f"split ehrenfest {which} n_orb={s.n_orb}")
+    gs = O.ground_state(s, tol=1e-13)
+    Sinv = O.inverse_overlap(s.S)
+    vel = W.thermal_velocities(s, 1500.0, seed=9)
+    field = W.sin2_pulse(np.arange(n) * 0.2, 0.01, 0.4, n * 0.2, (1.0, 0.5, 0.2))
+    e = T.Ehrenfest(s, m, velocities=vel, rho0=gs.rho, precision=T.TD_SPLIT_BF16, n_slices=4)
+    e.kick(1e-3, (0.0, 1.0, 0.0))
+    mu = e.step(n, field)
+    pos, _ = e.nuclei()
+    rk = O.kick(gs.rho, s.S, Sinv, s.positions, s.orb_offset, 1e-3, (0.0, 1.0, 0.0))
+    ref = OE.propagate(s, m, rk, vel, n, 0.2, field=field)
+    err = np.abs(mu - ref.dipoles).max() / np.abs(ref.dipoles - ref.dipoles[0]).max()
+    say(f"dipole relative difference {err:.2e}")
+    assert err < 1e-6
+    assert np.abs(pos - ref.positions).max() < 1e-6 * np.abs(ref.positions).max()
+    e.close()

@@ -100,9 +100,10 @@ def test_batch_errors():
     say("ehrenfest batch errors")
     o = T.td_default_options()
     o.precision = T.TD_SPLIT_BF16
+    o.n_slices = 6
     with pytest.raises(T.TdError) as e:
         T.td_batch_create_ehrenfest(s, m, 2, options=o)
-    assert e.value.status == T.TD_ENOTSUP and "member 0" in str(e.value)
+    assert e.value.status == T.TD_EINVAL and "member 0" in str(e.value)
     b = T.Batch([s])
     with pytest.raises(T.TdError) as e:
         T.td_batch_get_nuclei(b.b, 0, s.n_atoms)
@@ -114,3 +115,26 @@ def test_batch_errors():
         eb.step(1)
     assert e.value.status == T.TD_EUNSTABLE and "member 0" in str(e.value)
     eb.close()
+
+
+def test_split_members_equal_solo_runs():
+    """Split-bf16 moving-nuclei batch: each member's products with rho run
+    as in its solo context, so members equal solo runs bit for bit."""
+    T = _T()
+    s = W.benzene()
+    m = W.two_centre_model(s)
+    say("split ehrenfest batch benzene")
+    gs = O.ground_state(s, tol=1e-13)
+    vel = np.array([W.thermal_velocities(s, 800.0 + 400.0 * j, seed=30 + j) for j in range(2)])
+    n = 20
+    b = T.EhrenfestBatch(s, m, 2, velocities=vel, rho0=gs.rho, precision=T.TD_SPLIT_BF16)
+    b.kick(np.array([1e-3, 2e-3]), np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0]]))
+    b.step(n)
+    for j in range(2):
+        e = T.Ehrenfest(s, m, velocities=vel[j], rho0=gs.rho, precision=T.TD_SPLIT_BF16)
+        e.kick([1e-3, 2e-3][j], [[1.0, 0.0, 0.0], [0.0, 1.0, 0.0]][j])
+        mu = e.step(n)
+        assert np.array_equal(b.dipoles(j, n), mu), j
+        assert np.array_equal(b.nuclei(j)[0], e.nuclei()[0]), j
+        e.close()
+    b.close()
