@@ -72,7 +72,12 @@ typedef enum {
 /* td_system.flags: the array fields are device pointers (for example the
  * data of framework tensors) readable on td_options.hip_stream (or the
  * null stream when that is NULL); td_create reads them once, in stream
- * order, and keeps no reference. Without the flag they are host pointers. */
+ * order, and keeps no reference. Without the flag they are host pointers.
+ * S, H0, gamma and rho0 are copied device to device into the context's
+ * padded buffers and checked there (finite; S and H0 symmetric), with the
+ * same errors as host arrays; only the per-atom and per-shell arrays and
+ * occ pass through host memory. Batches and moving-nuclei contexts take
+ * host pointers only. */
 #define TD_DEVICE_PTRS 1u
 
 /* td_system.plus_u: the on-site corrections of Sec. 3.2 added to the SCC

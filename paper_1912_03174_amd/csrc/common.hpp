@@ -241,6 +241,10 @@ hipError_t trace(hipStream_t s, const double* X, int ld, int n, double* out);
 // out[0] = max_{i,j<n} |delta_ij - T_ij| (work: n doubles).
 hipError_t identity_residual(hipStream_t s, const double* T, int ld, int n, double* work,
                              double* out);
+// out[0] = +inf if M (rows x cols) holds a value that is not finite, else
+// max |M_ij - M_ji| when symmetric (rows == cols) or 0 (work: rows doubles).
+hipError_t check_matrix(hipStream_t s, const double* M, int ld, int rows, int cols,
+                        int symmetric, double* work, double* out);
 // Gershgorin bounds of T (n x n): out[0] = min(center - radius), out[1] = max(...).
 hipError_t gershgorin(hipStream_t s, const double* T, int ld, int n, double* work_lo,
                       double* work_hi, double* out);

@@ -381,6 +381,24 @@ __global__ __launch_bounds__(1024) void k_max(const double* __restrict__ x, int 
   if (threadIdx.x == 0) out[0] = m;
 }
 
+// Per row: +inf if the row holds a value that is not finite, else the
+// largest |M[r, c] - M[c, r]| (symmetric) or 0.
+__global__ __launch_bounds__(256) void k_row_check(const double* __restrict__ M, int ld, int rows,
+                                                   int cols, int symmetric,
+                                                   double* __restrict__ rowmax) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (row >= rows) return;
+  double m = 0.0;
+  for (int c = l; c < cols; c += WAVE) {
+    const double v = M[(size_t)row * ld + c];
+    if (!isfinite(v)) m = INFINITY;
+    else if (symmetric && c != row) m = fmax(m, fabs(v - M[(size_t)c * ld + row]));
+  }
+  m = wave_max(m);
+  if (l == 0) rowmax[row] = m;
+}
+
 __global__ __launch_bounds__(256) void k_row_gershgorin(const double* __restrict__ T, int ld,
                                                         int n, double* __restrict__ lo,
                                                         double* __restrict__ hi) {
@@ -806,6 +824,16 @@ hipError_t identity_residual(hipStream_t s, const double* T, int ld, int n, doub
                              double* out) {
   hipLaunchKernelGGL(k_row_identity_resid, dim3((n + 3) / 4), dim3(256), 0, s, T, ld, n, work);
   hipLaunchKernelGGL(k_max, dim3(1), dim3(1024), 0, s, work, n, out);
+  return hipGetLastError();
+}
+
+hipError_t check_matrix(hipStream_t s, const double* M, int ld, int rows, int cols,
+                        int symmetric, double* work, double* out) {
+  if (rows < 1 || cols < 1 || ld < cols || (symmetric && rows != cols))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_row_check, dim3((rows + 3) / 4), dim3(256), 0, s, M, ld, rows, cols,
+                     symmetric, work);
+  hipLaunchKernelGGL(k_max, dim3(1), dim3(1024), 0, s, work, rows, out);
   return hipGetLastError();
 }
 

@@ -408,7 +408,10 @@ void validate_plus_u(td_ctx* c, const td_system* s) {
   }
 }
 
-void validate(td_ctx* c, const td_system* s, const td_options* o) {
+// Checks of the model and options on the host. With `big_on_host` false the
+// n x n and n_atoms x n_atoms arrays (S, H0, gamma, rho0) are device
+// pointers, checked on the device after their copy (check_device_arrays).
+void validate(td_ctx* c, const td_system* s, const td_options* o, bool big_on_host) {
   REQUIRE(c, s && o, TD_EINVAL, "null system or options");
   REQUIRE(c, s->n_atoms > 0 && s->n_orb > 0, TD_EINVAL, "n_atoms and n_orb must be positive");
   REQUIRE(c, s->n_orb <= 65536, TD_EINVAL, "n_orb too large");
@@ -447,14 +450,15 @@ void validate(td_ctx* c, const td_system* s, const td_options* o) {
   REQUIRE(c, o->scc_tol > 0 && o->scc_maxiter > 0 && o->mix_beta > 0 && o->mix_beta <= 1,
           TD_EINVAL, "invalid SCC options");
   const size_t n = (size_t)s->n_orb, na = (size_t)s->n_atoms;
+  REQUIRE(c, finite_all(s->q0, na) && finite_all(s->positions, na * 3), TD_EINVAL,
+          "non-finite input values");
+  if (!big_on_host) return;
   REQUIRE(c, finite_all(s->S, n * n) && finite_all(s->H0, n * n) &&
-                 finite_all(s->gamma, na * na) && finite_all(s->q0, na) &&
-                 finite_all(s->positions, na * 3),
+                 finite_all(s->gamma, na * na),
           TD_EINVAL, "non-finite input values");
-  double smax = 0.0, asym = 0.0;
+  double asym = 0.0;
   for (size_t i = 0; i < n; ++i)
     for (size_t j = i + 1; j < n; ++j) {
-      smax = std::max(smax, std::fabs(s->S[i * n + j]));
       asym = std::max(asym, std::fabs(s->S[i * n + j] - s->S[j * n + i]));
       asym = std::max(asym, std::fabs(s->H0[i * n + j] - s->H0[j * n + i]));
     }
@@ -644,15 +648,17 @@ void full_density(td_ctx* c, const double* src, double* dst) {
   if (c->split) HIPCHK(c, td::wide_add_real(c->stream, dst, c->rho_ref, c->np, 1.0));
 }
 
-void upload_padded(td_ctx* c, const double* host, int n, double* dev, int np) {
-  HIPCHK(c, hipMemcpy2DAsync(dev, sizeof(double) * np, host, sizeof(double) * n,
-                             sizeof(double) * n, n, hipMemcpyHostToDevice, c->stream));
+void upload_padded(td_ctx* c, const double* src, int n, double* dev, int np,
+                   hipMemcpyKind kind = hipMemcpyHostToDevice) {
+  HIPCHK(c, hipMemcpy2DAsync(dev, sizeof(double) * np, src, sizeof(double) * n,
+                             sizeof(double) * n, n, kind, c->stream));
 }
 
-// Host copies of a model given by device pointers.
+// Host copies of the per-atom and per-shell arrays of a model given by
+// device pointers (the n x n and n_atoms x n_atoms arrays stay on the device).
 struct HostModel {
   std::vector<int32_t> orb_offset, shell_offset;
-  std::vector<double> positions, S, H0, gamma, q0, rho0, occ, shell_u;
+  std::vector<double> positions, q0, occ, shell_u;
 };
 
 template <class T>
@@ -662,8 +668,11 @@ void fetch(td_ctx* c, hipStream_t st, const T* src, size_t count, std::vector<T>
     HIPCHK(c, hipMemcpyAsync(dst.data(), src, sizeof(T) * count, hipMemcpyDeviceToHost, st));
 }
 
-// Reads a device-pointer model into host memory (stream order of `st`) and
-// returns a host-pointer view of it.
+// Reads the small arrays of a device-pointer model into host memory (stream
+// order of `st`, which is then drained, so that the device-to-device copies
+// of the large arrays on the context's stream follow every earlier write) and
+// returns a view with host pointers for them and the caller's device
+// pointers for S, H0, gamma and rho0.
 td_system host_view(td_ctx* c, const td_system* s, const td_options* o, HostModel& m) {
   REQUIRE(c, s && o, TD_EINVAL, "null system or options");
   REQUIRE(c, s->n_atoms > 0 && s->n_orb > 0 && s->n_orb <= 65536 && s->n_atoms <= s->n_orb,
@@ -674,11 +683,7 @@ td_system host_view(td_ctx* c, const td_system* s, const td_options* o, HostMode
   const size_t n = (size_t)s->n_orb, na = (size_t)s->n_atoms;
   fetch(c, st, s->orb_offset, na + 1, m.orb_offset);
   fetch(c, st, s->positions, 3 * na, m.positions);
-  fetch(c, st, s->S, n * n, m.S);
-  fetch(c, st, s->H0, n * n, m.H0);
-  fetch(c, st, s->gamma, na * na, m.gamma);
   fetch(c, st, s->q0, na, m.q0);
-  if (s->rho0) fetch(c, st, s->rho0, 2 * n * n, m.rho0);
   if (s->occ) fetch(c, st, s->occ, n, m.occ);
   const bool pu = s->plus_u != TD_PLUS_U_NONE && s->n_shells > 0 && s->n_shells <= s->n_orb;
   if (pu && s->shell_offset) fetch(c, st, s->shell_offset, (size_t)s->n_shells + 1, m.shell_offset);
@@ -687,16 +692,29 @@ td_system host_view(td_ctx* c, const td_system* s, const td_options* o, HostMode
   td_system h = *s;
   h.orb_offset = m.orb_offset.data();
   h.positions = m.positions.data();
-  h.S = m.S.data();
-  h.H0 = m.H0.data();
-  h.gamma = m.gamma.data();
   h.q0 = m.q0.data();
-  h.rho0 = s->rho0 ? m.rho0.data() : nullptr;
   h.occ = s->occ ? m.occ.data() : nullptr;
   h.shell_offset = (pu && s->shell_offset) ? m.shell_offset.data() : nullptr;
   h.shell_u = (pu && s->shell_u) ? m.shell_u.data() : nullptr;
-  h.flags = 0;
   return h;
+}
+
+// The device checks of the arrays copied device to device: S and H0
+// symmetric (to 1e-12) and finite, gamma and rho0 finite.
+void check_device_arrays(td_ctx* c, bool has_rho0) {
+  const int n = c->n, na = c->na, np = c->np;
+  HIPCHK(c, td::check_matrix(c->stream, c->S, np, n, n, 1, c->work1, c->scal + SC_TR1));
+  HIPCHK(c, td::check_matrix(c->stream, c->H0, np, n, n, 1, c->work1, c->scal + SC_TR2));
+  HIPCHK(c, td::check_matrix(c->stream, c->gamma, na, na, na, 0, c->work1, c->scal + SC_RES));
+  if (has_rho0)
+    HIPCHK(c, td::check_matrix(c->stream, c->X, 2 * n, n, 2 * n, 0, c->work1,
+                               c->scal + SC_NE));
+  double r[4] = {0, 0, 0, 0};
+  read_scal(c, SC_NE, r, 4);                           // SC_NE, SC_RES, SC_TR1, SC_TR2
+  REQUIRE(c, std::isfinite(r[1]) && std::isfinite(r[2]) && std::isfinite(r[3]), TD_EINVAL,
+          "non-finite input values");
+  REQUIRE(c, std::max(r[2], r[3]) <= 1e-12, TD_EINVAL, "S and H0 must be symmetric");
+  REQUIRE(c, !has_rho0 || std::isfinite(r[0]), TD_EINVAL, "non-finite rho0");
 }
 
 // Device copies of the shells, the shell of every orbital (-1 in the
@@ -815,11 +833,12 @@ void create_impl(td_ctx* c, const td_system* s_in, const td_options* o) {
   HostModel staged;
   td_system view;
   const td_system* s = s_in;
-  if (s_in->flags & TD_DEVICE_PTRS) {
+  const bool dev = (s_in->flags & TD_DEVICE_PTRS) != 0;
+  if (dev) {
     view = host_view(c, s_in, o, staged);
     s = &view;
   }
-  validate(c, s, o);
+  validate(c, s, o, !dev);
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   REQUIRE(c, e == hipSuccess && ndev > 0, TD_EHIP,
@@ -879,21 +898,22 @@ void create_impl(td_ctx* c, const td_system* s_in, const td_options* o) {
   HIPCHK(c, hipMemcpyAsync(c->pos, s->positions, sizeof(double) * 3 * na, hipMemcpyHostToDevice,
                            c->stream));
   HIPCHK(c, hipMemcpyAsync(c->q0, s->q0, sizeof(double) * na, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->gamma, s->gamma, sizeof(double) * na * na, hipMemcpyHostToDevice,
-                           c->stream));
-  upload_padded(c, s->S, n, c->S, np);
-  upload_padded(c, s->H0, n, c->H0, np);
+  const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  HIPCHK(c, hipMemcpyAsync(c->gamma, s->gamma, sizeof(double) * na * na, kind, c->stream));
+  upload_padded(c, s->S, n, c->S, np, kind);
+  upload_padded(c, s->H0, n, c->H0, np, kind);
+  if (s->rho0)   // staged in X (interleaved n x n) until the inverse is built
+    HIPCHK(c, hipMemcpyAsync(c->X, s->rho0, sizeof(double) * 2 * (size_t)n * n, kind,
+                             c->stream));
+  if (dev) check_device_arrays(c, s->rho0 != nullptr);
   if (s->plus_u != TD_PLUS_U_NONE) setup_plus_u(c, s);
   c->info.n_atoms = na;
   c->info.n_orb = n;
   c->info.n_pad = np;
   c->info.precision = o->precision;
+  if (s->rho0) HIPCHK(c, td::interleaved_to_wide(c->stream, c->X, n, c->rho_cur, np));
   inverse_overlap(c);
-  if (s->rho0) {
-    HIPCHK(c, hipMemcpyAsync(c->X, s->rho0, sizeof(double) * 2 * (size_t)n * n,
-                             hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, td::interleaved_to_wide(c->stream, c->X, n, c->rho_cur, np));
-  } else {
+  if (!s->rho0) {
     ground_state(c);
   }
   refresh(c, true);                        // charges of the initial state

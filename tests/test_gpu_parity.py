@@ -237,6 +237,48 @@ def test_occupations_and_device_tensors_give_the_same_run(flake):
     assert np.array_equal(runs[0], runs[2])
 
 
+def test_device_tensors_with_rho0_and_their_device_checks(flake):
+    """A start density handed over as a GPU tensor gives the host-array run
+    bit for bit; the device-side checks of the arrays copied device to
+    device (S and H0 symmetric, S, H0, gamma and rho0 finite) refuse bad
+    ones with the host path's errors."""
+    import torch
+    T = _T()
+    s, gs, _ = flake
+    say("device tensors: rho0 and checks")
+    p = T.Propagator(s, rho0=gs.rho)
+    p.kick(1e-3, (0.0, 0.0, 1.0))
+    ref = p.step(40)
+    p.close()
+    dev = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).cuda()
+
+    def create(S=s.S, H0=s.H0, gamma=s.gamma, rho0=gs.rho):
+        return T.td_create_from_tensors(dev(s.orb_offset, torch.int32), dev(s.positions), dev(S),
+                                        dev(H0), dev(gamma), dev(s.q0), n_elec=s.n_elec,
+                                        rho0=dev(rho0, torch.complex128))
+
+    ctx = create()
+    T.td_kick(ctx, 1e-3, (0.0, 0.0, 1.0))
+    T.td_step(ctx, 40)
+    got = T.td_get_dipole_series(ctx, 40)
+    T.td_destroy(ctx)
+    assert np.array_equal(got, ref)
+    S1 = s.S.copy()
+    S1[3, 7] += 1e-9
+    H1 = s.H0.copy()
+    H1[5, 5] = np.nan
+    g1 = s.gamma.copy()
+    g1[1, 2] = np.inf
+    r1 = gs.rho.astype(np.complex128)
+    r1[4, 9] = complex(0.0, np.nan)
+    for kw, text in ((dict(S=S1), "symmetric"), (dict(H0=H1), "non-finite input"),
+                     (dict(gamma=g1), "non-finite input"), (dict(rho0=r1), "non-finite rho0")):
+        with pytest.raises(T.TdError) as e:
+            create(**kw)
+        assert e.value.status == T.TD_EINVAL and text in str(e.value), (list(kw), str(e.value))
+    torch.cuda.synchronize()
+
+
 def test_electron_count_and_hermiticity_on_gpu(flake):
     T = _T()
     s, gs, Sinv = flake
