@@ -283,7 +283,7 @@ TD_API td_status td_util_gemm(int32_t precision, int32_t n_slices, int32_t m, in
  * TD_GEMM_NOALLOC_SCRATCH_BYTES per GPU, kept until the process ends. A
  * product needs 8 (m k + k n + m n) bytes of it in FP64 and
  * (8 + 2 s)(m k + n k) + 8 m n in split-bf16 with s slices (sizes padded
- * to the tiles: m, n to 128, k to 128 or 256), so up to
+ * to the 128-wide tiles), so up to
  * m = n = k = 1664 in FP64 and 1280 at s = 4; a larger one returns
  * TD_EINVAL before any device work.
  * Every call on a GPU uses that GPU's one array: calls that overlap on one

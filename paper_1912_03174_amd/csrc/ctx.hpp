@@ -51,9 +51,6 @@ struct td_ctx {
   bool split = false;
   int ns = 4;                  // slices of [S^-1 H | S^-1 dH] [rho - rho_ref ; rho_ref]
   int ns1 = 4;                 // slices of S^-1 dH
-  int kp = 0;                  // K of the split products: np rounded up to the
-                               // 256-long exact accumulation chunk; the slices of
-                               // k in [np, kp) stay zero
   double *rho_ref = nullptr;   // np x np real reference density (the initial state)
   double *Agsb = nullptr;      // S^-1 H_ref
   double *Xref = nullptr;      // np x 2np wide: (S^-1 H_ref) rho_ref | 0

@@ -15,10 +15,12 @@
 // A product of two slices is exact in fp32 (16 bits); so is the sum over
 // 256 values of k of the leading pair (1,1), accumulated on its own, and of
 // the two pairs (1,2), (2,1). Pairs with t_a + t_b <= S + 1 are kept.
-// Every 256 values of k (a chunk) the fp32 accumulators are added into an
-// fp64 accumulator with the row and column exponents of the current K
-// segment: one product may concatenate segments with different operand
-// scales along K (used for (S^-1 H) rho_delta + (S^-1 dH) rho_ref).
+// At every multiple of 256 in k and at the end of each K segment (so a
+// chunk is at most 256 long and never spans two segments) the fp32
+// accumulators are added into an fp64 accumulator with the row and column
+// exponents of the segment: one product may concatenate segments with
+// different operand scales along K (used for (S^-1 H) rho_delta +
+// (S^-1 dH) rho_ref).
 #include <cmath>
 
 #include "common.hpp"
@@ -32,6 +34,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int BM = 128, BN = 128, BK = 16;
 constexpr int CHUNK = 256;       // exact fp32 accumulation length of the leading pairs
+constexpr int KUNIT = 128;       // K, segment lengths: multiples of the tile width
 constexpr int GROUP_M = 8;
 
 template <int S>
@@ -44,7 +47,7 @@ struct SplitArgs {
   int ldr;
   const int* fR;        // [nseg][Ncols]
   int fR_stride;
-  int seg_len;          // K length of one segment (multiple of CHUNK)
+  int seg_len;          // K length of one segment (multiple of KUNIT)
   int k_lo, k_hi;       // K extent for tiles with n0 >= n_split / n0 < n_split
   int n_split;
   double* C;
@@ -249,10 +252,11 @@ __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
   }
 
   // Output layout of the 32x32 fp32 block: register e of lane l holds row
-  // 8 (e/4) + 4 (l/32) + e%4, column l%32.
-#define TD_SPLIT_FLUSH(k_chunk_start)                                                      \
+  // 8 (e/4) + 4 (l/32) + e%4, column l%32. `seg`: the K segment of the
+  // chunk being flushed (a chunk never spans two segments).
+#define TD_SPLIT_FLUSH(seg_of_chunk)                                                       \
   {                                                                                        \
-    const int seg = (k_chunk_start) / p.seg_len;                                           \
+    const int seg = (seg_of_chunk);                                                        \
     _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                        \
       const int fc = sh_f[seg][wn * 64 + j * 32 + l32] - 16;                               \
       _Pragma("unroll") for (int e = 0; e < 16; ++e) {                                     \
@@ -337,12 +341,14 @@ __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
                                                               0, 0);                       \
     if (FLUSH_OK) {                                                                        \
       const int k_next = ((kt) + 1) * BK;                                                  \
-      if (k_next % CHUNK == 0 || (kt) + 1 == nk) TD_SPLIT_FLUSH((kt) * BK - ((kt) * BK) % CHUNK) \
+      if ((k_next & (CHUNK - 1)) == 0 || k_next == p.seg_len || (kt) + 1 == nk)            \
+        TD_SPLIT_FLUSH(((kt) * BK >= p.seg_len) ? 1 : 0)   /* at most two segments */       \
     }                                                                                      \
   }
 
-  // nk is a multiple of CHUNK / BK = 16, so of STAGES; flushes fall on the
-  // last step of each unrolled group.
+  // K and the segment length are multiples of KUNIT (8 steps of BK), so nk
+  // is a multiple of STAGES and every chunk and segment ends on the last
+  // step of an unrolled group, where the flushes fall.
   for (int kt = 0; kt < nk; kt += STAGES) {
     if (STAGES == 4) {
       TD_SPLIT_STEP(st0, st3, kt, false)
@@ -612,7 +618,9 @@ hipError_t launch_slice(hipStream_t st, int mode, const SliceSrc& src, int rows,
 
 hipError_t split_gemm(hipStream_t st, int n_slices, const SplitGemm& g) {
   if (g.m % BM || g.n % BN || g.m <= 0 || g.n <= 0) return hipErrorInvalidValue;
-  if (g.seg_len % CHUNK || g.k_lo % CHUNK || g.k_hi % CHUNK || g.k_lo <= 0 || g.k_hi <= 0)
+  // one or two K segments of seg_len
+  const auto segs_ok = [&](int k) { return k == g.seg_len || k == 2 * g.seg_len; };
+  if (g.seg_len <= 0 || g.seg_len % KUNIT || !segs_ok(g.k_lo) || !segs_ok(g.k_hi))
     return hipErrorInvalidValue;
   if (g.ldl % (16 * n_slices) || g.ldr % (16 * n_slices)) return hipErrorInvalidValue;
   switch (n_slices) {

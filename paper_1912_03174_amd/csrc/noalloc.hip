@@ -114,10 +114,9 @@ td_status td_util_gemm_noalloc(int32_t precision, int32_t n_slices, int32_t m, i
   const bool split = precision == TD_SPLIT_BF16;
   if (split && (n_slices < 3 || n_slices > 5))
     return er.fail(TD_EINVAL, "n_slices must be 3, 4 or 5");
-  // padding as td_util_gemm: rows and columns to the 128-wide tile, K to the
-  // product's accumulation unit (128 in FP64, 256-long exact chunks split)
+  // padding as td_util_gemm: rows, columns and K to the 128-wide tile
   const int mp = td::round_up(m, td::kGemmTile), npd = td::round_up(n, td::kGemmTile);
-  const int kp = td::round_up(k, split ? 256 : td::kGemmTile);
+  const int kp = td::round_up(k, td::kGemmTile);
   const size_t sA = align256(sizeof(double) * mp * (size_t)kp);
   const size_t sB = align256(sizeof(double) * npd * (size_t)kp);
   const size_t sC = align256(sizeof(double) * mp * (size_t)npd);

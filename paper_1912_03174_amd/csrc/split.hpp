@@ -34,8 +34,8 @@ struct SliceSrc {
 // L: [m][ldl] bf16, row exponents eL[seg][m] (stride eL_stride);
 // R: [n][ldr] bf16 holding the right operand transposed, column exponents
 // fR[seg][n]. Tiles whose first column is < n_split use K = k_hi, the
-// others K = k_lo. m, n multiples of 128; K values and seg_len multiples of
-// 256; ldl, ldr multiples of 16 S.
+// others K = k_lo. m, n multiples of 128; seg_len a multiple of 128 and
+// each K value seg_len or 2 seg_len; ldl, ldr multiples of 16 S.
 struct SplitGemm {
   int m = 0, n = 0;
   const __bf16* L = nullptr;

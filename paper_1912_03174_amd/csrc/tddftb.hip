@@ -497,11 +497,10 @@ void split_init(td_ctx* c) {
   dalloc(c, &c->v_ref, na);
   dalloc(c, &c->band_ref, np);
   dalloc(c, &c->stage, 2 * m2);
-  const size_t mk = (size_t)np * c->kp;       // slices: np rows, K = kp (zeros beyond np)
-  salloc(c, &c->sl_sinv, (size_t)c->ns * mk);
-  salloc(c, &c->sl_dh, (size_t)c->ns * mk);
-  salloc(c, &c->sl_L2, (size_t)c->ns * 2 * mk);
-  salloc(c, &c->sl_R2, (size_t)c->ns * 4 * mk);
+  salloc(c, &c->sl_sinv, (size_t)c->ns * m2);
+  salloc(c, &c->sl_dh, (size_t)c->ns * m2);
+  salloc(c, &c->sl_L2, (size_t)c->ns * 2 * m2);
+  salloc(c, &c->sl_R2, (size_t)c->ns * 4 * m2);
   ialloc(c, &c->e_sinv, np);
   ialloc(c, &c->e_dh, np);
   ialloc(c, &c->e_L2, 2 * (size_t)np);
@@ -525,13 +524,13 @@ void split_init(td_ctx* c) {
   td::SliceSrc si;
   si.M0 = c->Sinv;
   si.ld0 = np;
-  const int S = c->ns, kp = c->kp;
-  slice(c, td::SLICE_PLAIN, si, np, np, c->sl_sinv, kp * c->ns1, c->e_sinv, c->ns1);
+  const int S = c->ns;
+  slice(c, td::SLICE_PLAIN, si, np, np, c->sl_sinv, np * c->ns1, c->e_sinv, c->ns1);
   td::SliceSrc sr;
   sr.M0 = c->rho_ref;
   sr.ld0 = np;
   // reference rows become K segment 1 of the second product's right operand
-  slice(c, td::SLICE_PLAIN, sr, np, np, c->sl_R2 + (size_t)kp * S, 2 * kp * S,
+  slice(c, td::SLICE_PLAIN, sr, np, np, c->sl_R2 + (size_t)np * S, 2 * np * S,
         c->e_R2 + 2 * np);
   (void)n;
 }
@@ -540,7 +539,7 @@ void split_init(td_ctx* c) {
 // sliced [delta_re + renorm | -delta_im], potential change, sliced dH,
 // B = S^-1 dH, sliced [A | B], X = A_ref rho_ref + [A | B][delta; rho_ref].
 void split_products(td_ctx* c, const double* E, hipEvent_t* ev) {
-  const int np = c->np, na = c->na, kp = c->kp;
+  const int np = c->np, na = c->na;
   hipStream_t st = c->stream;
   const int S = c->ns, S1 = c->ns1;    // slices of the second and of the first product
   // [delta_re + renorm | -delta_im] (renormalises delta_re in place)
@@ -552,12 +551,12 @@ void split_products(td_ctx* c, const double* E, hipEvent_t* ev) {
     sdr.M1 = c->rho_ref;
     sdr.ld1 = np;
     sdr.cs = c->scal + SC_RENORM;
-    slice(c, td::SLICE_RENORM, sdr, np, np, c->sl_R2, 2 * kp * S, c->e_R2);
+    slice(c, td::SLICE_RENORM, sdr, np, np, c->sl_R2, 2 * np * S, c->e_R2);
     td::SliceSrc sdi;
     sdi.M0 = c->rho_cur + np;
     sdi.ld0 = 2 * np;
     sdi.sign = -1.0;
-    slice(c, td::SLICE_PLAIN, sdi, np, np, c->sl_R2 + (size_t)np * 2 * kp * S, 2 * kp * S,
+    slice(c, td::SLICE_PLAIN, sdi, np, np, c->sl_R2 + (size_t)np * 2 * np * S, 2 * np * S,
           c->e_R2 + np);
   };
   // right after the charges pass has read the density, while its lines are
@@ -579,23 +578,23 @@ void split_products(td_ctx* c, const double* E, hipEvent_t* ev) {
     td::SliceSrc sa;
     sa.M0 = c->A;
     sa.ld0 = np;
-    slice(c, td::SLICE_PLAIN, sa, np, np, c->sl_dh, kp * S1, c->e_dh, S1);
+    slice(c, td::SLICE_PLAIN, sa, np, np, c->sl_dh, np * S1, c->e_dh, S1);
     slice_density();
   } else {
-    slice(c, td::SLICE_DH, sdh, np, np, c->sl_dh, kp * S1, c->e_dh, S1);
+    slice(c, td::SLICE_DH, sdh, np, np, c->sl_dh, np * S1, c->e_dh, S1);
   }
   td::SplitGemm g1;
   g1.m = np;
   g1.n = np;
   g1.L = c->sl_sinv;
-  g1.ldl = kp * S1;
+  g1.ldl = np * S1;
   g1.eL = c->e_sinv;
   g1.R = c->sl_dh;
-  g1.ldr = kp * S1;
+  g1.ldr = np * S1;
   g1.fR = c->e_dh;
-  g1.seg_len = kp;
-  g1.k_lo = kp;
-  g1.k_hi = kp;
+  g1.seg_len = np;
+  g1.k_lo = np;
+  g1.k_hi = np;
   g1.n_split = np;
   g1.C = c->H;            // B = S^-1 dH
   g1.ldc = np;
@@ -609,30 +608,30 @@ void split_products(td_ctx* c, const double* E, hipEvent_t* ev) {
   sa.ld1 = np;
   if (np <= 4096) {
     // [A_ref + B | B] from one read of B
-    sa.out2 = c->sl_L2 + (size_t)kp * S;
+    sa.out2 = c->sl_L2 + (size_t)np * S;
     sa.exps2 = c->e_L2 + np;
-    slice(c, td::SLICE_SUM_AND_M1, sa, np, np, c->sl_L2, 2 * kp * S, c->e_L2);
+    slice(c, td::SLICE_SUM_AND_M1, sa, np, np, c->sl_L2, 2 * np * S, c->e_L2);
   } else {
-    slice(c, td::SLICE_SUM, sa, np, np, c->sl_L2, 2 * kp * S, c->e_L2);
+    slice(c, td::SLICE_SUM, sa, np, np, c->sl_L2, 2 * np * S, c->e_L2);
     td::SliceSrc sb;
     sb.M0 = c->H;
     sb.ld0 = np;
-    slice(c, td::SLICE_PLAIN, sb, np, np, c->sl_L2 + (size_t)kp * S, 2 * kp * S, c->e_L2 + np);
+    slice(c, td::SLICE_PLAIN, sb, np, np, c->sl_L2 + (size_t)np * S, 2 * np * S, c->e_L2 + np);
   }
   td::SplitGemm g2;
   g2.m = np;
   g2.n = 2 * np;
   g2.L = c->sl_L2;
-  g2.ldl = 2 * kp * S;
+  g2.ldl = 2 * np * S;
   g2.eL = c->e_L2;
   g2.eL_stride = np;
   g2.R = c->sl_R2;
-  g2.ldr = 2 * kp * S;
+  g2.ldr = 2 * np * S;
   g2.fR = c->e_R2;
   g2.fR_stride = 2 * np;
-  g2.seg_len = kp;
-  g2.k_hi = 2 * kp;     // real columns: A delta_re + B rho_ref
-  g2.k_lo = kp;         // imaginary columns: A delta_im
+  g2.seg_len = np;
+  g2.k_hi = 2 * np;     // real columns: A delta_re + B rho_ref
+  g2.k_lo = np;         // imaginary columns: A delta_im
   g2.n_split = np;
   g2.C = c->X;            // without X_ref: the update adds it (real part only)
   g2.ldc = 2 * np;
@@ -852,10 +851,9 @@ void create_impl(td_ctx* c, const td_system* s_in, const td_options* o) {
   const bool want_split = o->precision == TD_SPLIT_BF16;
   c->ns = o->n_slices;
   c->ns1 = o->n_slices_dh ? o->n_slices_dh : o->n_slices;
-  // every matrix at the 128-wide tile; only the split products' K (the
-  // slices) runs on to the 256-long exact accumulation chunk
+  // every matrix at the 128-wide tile, in both precisions (the split
+  // products' exact chunks restart at each K segment and may end short)
   c->np = round_up(s->n_orb, td::kPad);
-  c->kp = round_up(c->np, 256);
   if (s->occ) {
     int n2 = 0;
     while (n2 < s->n_orb && s->occ[n2] == 2.0) ++n2;
@@ -980,34 +978,34 @@ void rebuild_model(td_ctx* c, bool warm) {
 // `slice_rho` false the slices of rho from the previous call are reused
 // (rho unchanged in between).
 void ehr_split_product(td_ctx* c, const double* A, double* out, bool slice_rho) {
-  const int np = c->np, S = c->ns, kp = c->kp;
+  const int np = c->np, S = c->ns;
   if (slice_rho) {
     td::SliceSrc re;
     re.M0 = c->rho_cur;
     re.ld0 = 2 * np;
-    slice(c, td::SLICE_PLAIN, re, np, np, c->sl_R2, kp * S, c->e_R2);
+    slice(c, td::SLICE_PLAIN, re, np, np, c->sl_R2, np * S, c->e_R2);
     td::SliceSrc im;
     im.M0 = c->rho_cur + np;
     im.ld0 = 2 * np;
     im.sign = -1.0;
-    slice(c, td::SLICE_PLAIN, im, np, np, c->sl_R2 + (size_t)np * kp * S, kp * S, c->e_R2 + np);
+    slice(c, td::SLICE_PLAIN, im, np, np, c->sl_R2 + (size_t)np * np * S, np * S, c->e_R2 + np);
   }
   td::SliceSrc a;
   a.M0 = A;
   a.ld0 = np;
-  slice(c, td::SLICE_PLAIN, a, np, np, c->sl_L2, kp * S, c->e_L2);
+  slice(c, td::SLICE_PLAIN, a, np, np, c->sl_L2, np * S, c->e_L2);
   td::SplitGemm g;
   g.m = np;
   g.n = 2 * np;
   g.L = c->sl_L2;
-  g.ldl = kp * S;
+  g.ldl = np * S;
   g.eL = c->e_L2;
   g.R = c->sl_R2;
-  g.ldr = kp * S;
+  g.ldr = np * S;
   g.fR = c->e_R2;
-  g.seg_len = kp;
-  g.k_lo = kp;
-  g.k_hi = kp;
+  g.seg_len = np;
+  g.k_lo = np;
+  g.k_hi = np;
   g.n_split = 2 * np;
   g.C = out;
   g.ldc = 2 * np;
@@ -1244,7 +1242,7 @@ void kick_impl(td_ctx* c, double e0, const double* dir) {
 // (B transposed on the host) are sliced on the device.
 void split_gemm_host(td_ctx* c, int ns, int m, int n, int k, const double* A, const double* B,
                      double* C) {
-  const int mp = round_up(m, 128), npd = round_up(n, 128), kp = round_up(k, 256);
+  const int mp = round_up(m, 128), npd = round_up(n, 128), kp = round_up(k, 128);
   std::vector<double> bt((size_t)n * k);
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < n; ++j) bt[(size_t)j * k + i] = B[(size_t)i * n + j];
@@ -1445,8 +1443,8 @@ void create_ehr_impl(td_ctx* c, const td_system* s, const td_model* m, const dou
   upload_model(c, s, m, vel);
   const size_t m2 = (size_t)c->np * c->np;
   if (o->precision == TD_SPLIT_BF16) {
-    salloc(c, &c->sl_L2, (size_t)c->ns * c->np * c->kp);
-    salloc(c, &c->sl_R2, (size_t)c->ns * 2 * c->np * c->kp);
+    salloc(c, &c->sl_L2, (size_t)c->ns * m2);
+    salloc(c, &c->sl_R2, (size_t)c->ns * 2 * m2);
     ialloc(c, &c->e_L2, c->np);
     ialloc(c, &c->e_R2, 2 * (size_t)c->np);
     c->ehr_split = true;
