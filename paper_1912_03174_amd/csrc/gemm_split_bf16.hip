@@ -147,7 +147,10 @@ __device__ __forceinline__ void read_frags(Frags<S>& f, uint32_t base, const uin
   }
 }
 
-template <int S>
+// SEG256: the segment length is a multiple of CHUNK, so chunks end only at
+// multiples of CHUNK and the segment of a chunk follows from its start (the
+// N_orb = 4096 case); otherwise a chunk also ends at the segment boundary.
+template <int S, bool SEG256>
 __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
   // LDS ring of STAGES separate arrays (so the compiler can see that the
   // direct-to-LDS loads into one stage do not alias the fragment reads of
@@ -341,8 +344,13 @@ __global__ __launch_bounds__(512) void sgemm_split(SplitArgs<S> p) {
                                                               0, 0);                       \
     if (FLUSH_OK) {                                                                        \
       const int k_next = ((kt) + 1) * BK;                                                  \
-      if ((k_next & (CHUNK - 1)) == 0 || k_next == p.seg_len || (kt) + 1 == nk)            \
-        TD_SPLIT_FLUSH(((kt) * BK >= p.seg_len) ? 1 : 0)   /* at most two segments */       \
+      if constexpr (SEG256) {                                                              \
+        if (k_next % CHUNK == 0 || (kt) + 1 == nk)                                         \
+          TD_SPLIT_FLUSH(((kt) * BK - ((kt) * BK) % CHUNK) / p.seg_len)                    \
+      } else {                                                                             \
+        if ((k_next & (CHUNK - 1)) == 0 || k_next == p.seg_len || (kt) + 1 == nk)          \
+          TD_SPLIT_FLUSH(((kt) * BK >= p.seg_len) ? 1 : 0)   /* at most two segments */     \
+      }                                                                                    \
     }                                                                                      \
   }
 
@@ -439,7 +447,10 @@ hipError_t launch_split(hipStream_t st, const SplitGemm& g) {
   p.ldcin = g.ldcin;
   p.tiles_m = g.m / BM;
   p.tiles_n = g.n / BN;
-  hipLaunchKernelGGL(sgemm_split<S>, dim3(p.tiles_m * p.tiles_n), dim3(512), 0, st, p);
+  if (g.seg_len % CHUNK == 0)
+    hipLaunchKernelGGL((sgemm_split<S, true>), dim3(p.tiles_m * p.tiles_n), dim3(512), 0, st, p);
+  else
+    hipLaunchKernelGGL((sgemm_split<S, false>), dim3(p.tiles_m * p.tiles_n), dim3(512), 0, st, p);
   return hipGetLastError();
 }
 
