@@ -852,7 +852,8 @@ void create_impl(td_ctx* c, const td_system* s_in, const td_options* o) {
   c->ns = o->n_slices;
   c->ns1 = o->n_slices_dh ? o->n_slices_dh : o->n_slices;
   // every matrix at the 128-wide tile, in both precisions (the split
-  // products' exact chunks restart at each K segment and may end short)
+  // products' exact chunks also end at K segment boundaries, so K needs no
+  // coarser padding)
   c->np = round_up(s->n_orb, td::kPad);
   if (s->occ) {
     int n2 = 0;
