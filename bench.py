@@ -436,7 +436,8 @@ def ehrenfest(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": first["ms_per_step"],
         "dtype": "f64" if precs[0] == "fp64" else "bf16",
         "config": {"workload": w.name, "n_orb": n, "n_atoms": s.n_atoms,
-                   "field": "sin^2 pump 0.15 Ha, 0.01 au, 10 fs", "nuclei": "300 K"},
+                   "field": "sin^2 pump 0.15 Ha, 0.01 au, 10 fs, across the strip",
+                   "nuclei": "300 K"},
         "precisions": {k: {kk: vv for kk, vv in v.items() if kk != "dipoles"}
                        for k, v in runs.items()},
     }), flush=True)
@@ -491,7 +492,8 @@ def ehrenfest_batch(args):
         "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True,
         "dtype": "bf16" if split else "f64", "data": "synthetic",
         "config": {"workload": f"{w.name} x{nm}", "members": nm, "n_orb": n,
-                   "n_atoms": s.n_atoms, "field": "sin^2 pump 0.15 Ha, 0.01 au, 10 fs",
+                   "n_atoms": s.n_atoms,
+                   "field": "sin^2 pump 0.15 Ha, 0.01 au, 10 fs, across the strip",
                    "nuclei": "300 K, velocity seeds 5000 ..", "parallelism": "single GPU"},
         "product_tflops": flop * rate / 1e12,
         "fp64_peak_frac": flop * rate / 1e12 / FP64_PEAK_TFLOPS,

@@ -229,7 +229,8 @@ TD_API td_status td_get_dipole_series(td_ctx *ctx, double *mu, int32_t cap, int3
 
 /* Energy of the current rho: Re Tr(rho H0) + 1/2 dq gamma dq
  * + sum_A dq_A R_A . field (field may be NULL for zero) (Sec. 2.1,
- * Eqs. 2-3). */
+ * Eqs. 2-3); with moving nuclei, plus the model's repulsive energy E_rep
+ * at the current positions. */
 TD_API td_status td_get_energy(td_ctx *ctx, const double field[3], double *energy);
 
 /* Checkpoint: current and previous density matrices as [n_orb * n_orb]
@@ -309,7 +310,8 @@ TD_API td_status td_util_gemm_noalloc(int32_t precision, int32_t n_slices, int32
  * +1/2 Re Tr{rho ((grad S) S^-1 H + H S^-1 (grad S))} (the sign that
  * conserves electronic plus nuclear kinetic energy and reduces to the
  * ground-state energy gradient), the SCC term with the Hamiltonian's full
- * atomic potential (gamma dq + R . E). No repulsive energy. */
+ * atomic potential (gamma dq + R . E), and the repulsive term -grad_A E_rep
+ * of the model's pair repulsion (td_model.rep_a). */
 
 /* Two-centre model: every off-site integral between orbital i of atom a
  * and orbital j of atom b at d = R_b - R_a is
@@ -319,7 +321,12 @@ TD_API td_status td_util_gemm_noalloc(int32_t precision, int32_t n_slices, int32
  * s-on-b element uses the (sb, sa) sp prefactor with d reversed. On-site:
  * S = 1, H0 = onsite[s][0] (s) or onsite[s][1] (p), no on-site coupling.
  * gamma_AB = 1 / sqrt(r^2 + hubbard_u^-2). Orbitals per atom: s, or s,
- * p_x, p_y, p_z, in that order, consistent with td_system.orb_offset. */
+ * p_x, p_y, p_z, in that order, consistent with td_system.orb_offset.
+ * Repulsive energy (Sec. 2.1: the pairwise E_rep of the total energy):
+ *   E_rep = sum_{A<B} rep_a[s_A, s_B] exp(-r_AB / rep_decay),
+ * every pair, no cutoff; rep_a NULL means none. It adds -grad_A E_rep to
+ * the forces and E_rep to the energies (td_get_energy, the energy
+ * series). */
 typedef struct {
   int32_t n_species;
   const int32_t *species;        /* [n_atoms], values in [0, n_species)              */
@@ -332,6 +339,9 @@ typedef struct {
   const double *onsite;          /* [n_species * 2] hartree                          */
   double hubbard_u;              /* hartree, > 0                                     */
   const double *mass;            /* [n_species] electron masses, > 0                 */
+  const double *rep_a;           /* [n_species * n_species] hartree, symmetric,      */
+                                 /* finite, >= 0; NULL: no repulsion                 */
+  double rep_decay;              /* bohr, > 0 when rep_a is given                    */
 } td_model;
 
 /* Creates a context with moving nuclei. sys gives positions, orb_offset,
@@ -355,10 +365,11 @@ TD_API td_status td_create_ehrenfest(const td_system *sys, const td_model *model
  * step behind the positions (v_{n-1/2}). Any pointer may be NULL. */
 TD_API td_status td_get_nuclei(td_ctx *ctx, double *positions, double *velocities);
 
-/* Per step of the last td_step on a moving-nuclei context: electronic
- * energy e_el[k] (as td_get_energy, at the step's field) of the density
- * entering step k and the nuclear kinetic energy e_kin[k] of the velocities
- * at that step; k < min(cap, n); *n_out = number recorded. */
+/* Per step of the last td_step on a moving-nuclei context: energy e_el[k]
+ * (as td_get_energy, at the step's field: electronic terms plus E_rep) of
+ * the density and positions entering step k and the nuclear kinetic energy
+ * e_kin[k] of the velocities at that step; k < min(cap, n); *n_out =
+ * number recorded. */
 TD_API td_status td_get_energy_series(td_ctx *ctx, double *e_el, double *e_kin, int32_t cap,
                                       int32_t *n_out);
 

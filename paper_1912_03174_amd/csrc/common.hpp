@@ -141,6 +141,11 @@ hipError_t kick_nuclei(hipStream_t s, double* vel, const double* F, const int* s
 hipError_t drift_nuclei(hipStream_t s, double* pos, const double* vel, int na, double dt);
 hipError_t kinetic_energy(hipStream_t s, const double* vel, const double* F, const int* species,
                           const double* mass, int na, double h, double* out);
+// Pair repulsion E_rep = sum_{A<B} rep_a[s_A, s_B] exp(-r_AB / decay): adds
+// -grad_A E_rep to F (if not null) and writes E_rep to *energy, summed in a
+// fixed order from the per-atom halves in e_atom [na].
+hipError_t repulsion(hipStream_t s, const double* pos, const int* species, const double* rep_a,
+                     int nsp, double decay, int na, double* F, double* e_atom, double* energy);
 
 // ---------------------------------------------------------------- O(n^2) kernels
 // out[r] = sum_c X[r, c] * Y[r, c] for r < rows (cols multiple of 2).

@@ -72,6 +72,9 @@ struct td_ctx {
   int *species = nullptr, *norb = nullptr, *atom_of = nullptr;
   double *sk_s = nullptr, *sk_h = nullptr, *scale_s = nullptr, *scale_h = nullptr;
   double *onsite = nullptr, *mass = nullptr;
+  double *rep_a = nullptr;               // nsp x nsp pair repulsion amplitudes (or none)
+  double rep_decay = 0.0;
+  double *e_rep_atom = nullptr;          // na: per-atom halves of the pair repulsion
   double *GS = nullptr, *GH = nullptr;   // 3 np x np each
   double *W = nullptr, *Dm = nullptr;    // np x np
   double *Sinv_prev = nullptr;           // np x np: S^-1 of the previous positions
@@ -80,7 +83,8 @@ struct td_ctx {
   double *Z = nullptr;                   // np x 2np
   double *dgamma = nullptr;              // na x na x 3
   double *vel = nullptr, *F = nullptr;   // na x 3
-  double *e_kin = nullptr, *e_el = nullptr;   // per-step series (dip_cap)
+  double *e_kin = nullptr, *e_el = nullptr;   // per-step series (dip_cap); e_el holds
+                                              // 4 terms a step: band, Coulomb, field, E_rep
   // profiling
   std::vector<hipEvent_t> ev;
   double kt_ms[TD_KT_COUNT] = {0, 0, 0, 0};

@@ -233,6 +233,47 @@ hipError_t nac_build(hipStream_t s, const double* GS, const double* vel, const i
   return hipGetLastError();
 }
 
+// One wave per atom A, its lanes over the other atoms B: the pair term
+// w = rep_a[s_A, s_B] exp(-r / decay), its force on A
+// (w / decay) (R_A - R_B) / r (Sec. 2.1, the -grad_A E_rep of Eq. 15) and
+// half of w (each pair is seen from both atoms), summed by a fixed-order
+// wave reduction.
+__global__ __launch_bounds__(256) void k_repulsion(const double* __restrict__ pos,
+                                                   const int* __restrict__ species,
+                                                   const double* __restrict__ rep_a, int nsp,
+                                                   double decay, int na, double* F,
+                                                   double* __restrict__ e_atom) {
+  const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (a >= na) return;
+  const double xa = pos[3 * a], ya = pos[3 * a + 1], za = pos[3 * a + 2];
+  const double* row = rep_a + (size_t)species[a] * nsp;
+  double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
+  for (int b = l; b < na; b += 64) {
+    if (b == a) continue;
+    const double dx = xa - pos[3 * b], dy = ya - pos[3 * b + 1], dz = za - pos[3 * b + 2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    const double w = row[species[b]] * exp(-r / decay);
+    const double g = w / (decay * r);
+    fx += g * dx;
+    fy += g * dy;
+    fz += g * dz;
+    e += 0.5 * w;
+  }
+  fx = wave_sum(fx);
+  fy = wave_sum(fy);
+  fz = wave_sum(fz);
+  e = wave_sum(e);
+  if (l == 0) {
+    if (F) {
+      F[3 * a] += fx;
+      F[3 * a + 1] += fy;
+      F[3 * a + 2] += fz;
+    }
+    e_atom[a] = e;
+  }
+}
+
 hipError_t ehrenfest_forces(hipStream_t s, const double* rho, int ldr, const double* W,
                             const double* GS, const double* GH, const double* vorb,
                             const int* orb_off, const double* dq, const double* dgamma,
@@ -252,6 +293,17 @@ hipError_t kick_nuclei(hipStream_t s, double* vel, const double* F, const int* s
 hipError_t drift_nuclei(hipStream_t s, double* pos, const double* vel, int na, double dt) {
   hipLaunchKernelGGL(k_drift, dim3(nblocks((size_t)3 * na)), dim3(256), 0, s, pos, vel, na, dt);
   return hipGetLastError();
+}
+
+hipError_t repulsion(hipStream_t s, const double* pos, const int* species, const double* rep_a,
+                     int nsp, double decay, int na, double* F, double* e_atom, double* energy) {
+  if (na <= 0 || nsp <= 0 || !(decay > 0.0) || !rep_a || !e_atom || !energy)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_repulsion, dim3((na + 3) / 4), dim3(256), 0, s, pos, species, rep_a, nsp,
+                     decay, na, F, e_atom);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return sum_vector(s, e_atom, na, energy);
 }
 
 hipError_t kinetic_energy(hipStream_t s, const double* vel, const double* F, const int* species,

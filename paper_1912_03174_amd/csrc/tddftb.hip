@@ -30,7 +30,7 @@ namespace {
 
 // scal[] slots
 enum { SC_MU = 0, SC_NE = 3, SC_RES = 4, SC_TR1 = 5, SC_TR2 = 6, SC_BOUNDS = 8, SC_E = 10,
-       SC_RENORM = 13, SC_FIELD = 16, SC_COUNT = 32 };
+       SC_RENORM = 13, SC_FIELD = 16, SC_EREP = 20, SC_COUNT = 32 };
 
 using tdi::Fail;
 using tdi::guarded;
@@ -67,6 +67,7 @@ void free_all(td_ctx* c) {
     *b = nullptr;
   }
   double** ebufs[] = {&c->sk_s, &c->sk_h, &c->scale_s, &c->scale_h, &c->onsite, &c->mass,
+                      &c->rep_a, &c->e_rep_atom,
                       &c->GS, &c->GH, &c->W, &c->Dm, &c->Sinv_prev, &c->Sinv_prev2, &c->Z, &c->dgamma,
                       &c->vel, &c->F,
                       &c->e_kin, &c->e_el, &c->sh_u, &c->sh_n, &c->sh_v, &c->sh_e,
@@ -1026,12 +1027,17 @@ void ehr_phase_h(td_ctx* c, const double* E, double* mu, double* energy3) {
   HIPCHK(c, td::assemble_h(st, c->H0, c->S, c->vorb, c->H, np));
 }
 
-void ehr_phase_forces(td_ctx* c, const double* E) {
+// energy4: the step's four energy terms (band, Coulomb, field, E_rep), or
+// null when no energy is recorded.
+void ehr_phase_forces(td_ctx* c, const double* E, double* energy4) {
   hipStream_t st = c->stream;
   const int np = c->np;
   HIPCHK(c, td::pair_sym(st, c->X, 2 * np, c->W, nullptr, np, np));
   HIPCHK(c, td::ehrenfest_forces(st, c->rho_cur, 2 * np, c->W, c->GS, c->GH, c->vorb, c->orb_off,
                                  c->dq, c->dgamma, E, c->na, c->n, np, c->F));
+  if (c->rep_a)   // -grad E_rep (Eq. 15) and E_rep itself
+    HIPCHK(c, td::repulsion(st, c->pos, c->species, c->rep_a, c->nsp, c->rep_decay, c->na, c->F,
+                            c->e_rep_atom, energy4 ? energy4 + 3 : c->scal + SC_EREP));
 }
 
 void ehr_phase_nac(td_ctx* c, int k) {
@@ -1068,15 +1074,15 @@ void ehr_phase_move(td_ctx* c) {
 
 // Charges (dipole -> mu), H with field E, X = (S^-1 H) rho_cur, W = sym Re X and
 // the forces F of the current state (Sec. 2.1, Eq. 15 without velocity terms).
-void ehr_forces(td_ctx* c, const double* E, double* mu, double* energy3) {
+void ehr_forces(td_ctx* c, const double* E, double* mu, double* energy4) {
   const int np = c->np;
-  ehr_phase_h(c, E, mu, energy3);
+  ehr_phase_h(c, E, mu, energy4);
   gemm(c, 1, np, np, np, 1.0, c->Sinv, np, c->H, np, c->A, np);
   if (c->ehr_split)
     ehr_split_product(c, c->A, c->X, true);
   else
     gemm(c, 2, np, 2 * np, np, 1.0, c->A, np, c->rho_cur, 2 * np, c->X, 2 * np);
-  ehr_phase_forces(c, E);
+  ehr_phase_forces(c, E, energy4);
 }
 
 // One Ehrenfest step k (model matrices current at R_k): forces, velocity
@@ -1084,7 +1090,7 @@ void ehr_forces(td_ctx* c, const double* E, double* mu, double* energy3) {
 // Eqs. 10, 14, 15; Sec. 2.3, Eq. 19), then the matrices at R_{k+1}.
 void ehr_step(td_ctx* c, int k, const double* E) {
   const int np = c->np;
-  ehr_forces(c, E, c->dip + 3 * (size_t)k, c->e_el + 3 * (size_t)k);
+  ehr_forces(c, E, c->dip + 3 * (size_t)k, c->e_el + 4 * (size_t)k);
   ehr_phase_nac(c, k);
   // X += -i S^-1 D rho with D from v_k
   gemm(c, 0, np, np, np, 1.0, c->Sinv, np, c->Dm, np, c->A, np);
@@ -1109,7 +1115,7 @@ void ensure_series(td_ctx* c, int nsteps) {
     if (c->e_el) (void)hipFree(c->e_el);
     c->e_kin = c->e_el = nullptr;
     dalloc(c, &c->e_kin, (size_t)nsteps);
-    dalloc(c, &c->e_el, 3 * (size_t)nsteps);
+    dalloc(c, &c->e_el, 4 * (size_t)nsteps);
   }
   c->dip_cap = nsteps;
 }
@@ -1328,6 +1334,15 @@ void validate_model(td_ctx* c, const td_system* s, const td_model* m) {
                  finite_all(m->scale_s, (size_t)na * na) && finite_all(m->scale_h, (size_t)na * na) &&
                  finite_all(s->positions, (size_t)na * 3),
           TD_EINVAL, "non-finite model or positions");
+  if (m->rep_a) {
+    REQUIRE(c, finite_all(m->rep_a, (size_t)nsp * nsp) && m->rep_decay > 0 &&
+                   std::isfinite(m->rep_decay),
+            TD_EINVAL, "rep_a must be finite and rep_decay positive");
+    for (int i = 0; i < nsp; ++i)
+      for (int j = 0; j < nsp; ++j)
+        REQUIRE(c, m->rep_a[i * nsp + j] >= 0 && m->rep_a[i * nsp + j] == m->rep_a[j * nsp + i],
+                TD_EINVAL, "rep_a must be symmetric and non-negative");
+  }
   for (int a = 0; a < na; ++a)
     for (int b = a + 1; b < na; ++b) {
       const double* p = s->positions;
@@ -1352,6 +1367,11 @@ void upload_model(td_ctx* c, const td_system* s, const td_model* m, const double
   dalloc(c, &c->scale_h, (size_t)na * na);
   dalloc(c, &c->onsite, (size_t)nsp * 2);
   dalloc(c, &c->mass, nsp);
+  if (m->rep_a) {
+    dalloc(c, &c->rep_a, (size_t)nsp * nsp);
+    dalloc(c, &c->e_rep_atom, na);
+    c->rep_decay = m->rep_decay;
+  }
   dalloc(c, &c->GS, 3 * (size_t)c->np * c->np);
   dalloc(c, &c->GH, 3 * (size_t)c->np * c->np);
   dalloc(c, &c->dgamma, 3 * (size_t)na * na);
@@ -1371,6 +1391,9 @@ void upload_model(td_ctx* c, const td_system* s, const td_model* m, const double
   HIPCHK(c, hipMemcpyAsync(c->scale_h, m->scale_h, sizeof(double) * na * na, hipMemcpyHostToDevice, st));
   HIPCHK(c, hipMemcpyAsync(c->onsite, m->onsite, sizeof(double) * nsp * 2, hipMemcpyHostToDevice, st));
   HIPCHK(c, hipMemcpyAsync(c->mass, m->mass, sizeof(double) * nsp, hipMemcpyHostToDevice, st));
+  if (m->rep_a)
+    HIPCHK(c, hipMemcpyAsync(c->rep_a, m->rep_a, sizeof(double) * nsp * nsp,
+                             hipMemcpyHostToDevice, st));
   if (vel)
     HIPCHK(c, hipMemcpyAsync(c->vel, vel, sizeof(double) * 3 * na, hipMemcpyHostToDevice, st));
 }
@@ -1577,7 +1600,7 @@ void ehr_batch_steps(std::vector<td_ctx*>& mem, EhrGroup& g, int nsteps, const d
   g.used = 0;
   for (int k = 0; k < nsteps; ++k) {
     const double* E = field ? field + 3 * (size_t)k : nullptr;
-    each([&](td_ctx* c, int) { ehr_phase_h(c, E, c->dip + 3 * (size_t)k, c->e_el + 3 * (size_t)k); });
+    each([&](td_ctx* c, int) { ehr_phase_h(c, E, c->dip + 3 * (size_t)k, c->e_el + 4 * (size_t)k); });
     for (td_ctx* c : mem) pr.push_back(problem(c->Sinv, np, c->H, np, c->A, np, np, np, np, T, 0));
     grouped_launch(c0, g, pr, T);                                   // A = S^-1 H
     if (c0->ehr_split) {
@@ -1588,7 +1611,7 @@ void ehr_batch_steps(std::vector<td_ctx*>& mem, EhrGroup& g, int nsteps, const d
       grouped_launch(c0, g, pr, T);                                 // X = A rho
     }
     each([&](td_ctx* c, int) {
-      ehr_phase_forces(c, E);
+      ehr_phase_forces(c, E, c->e_el + 4 * (size_t)k);
       ehr_phase_nac(c, k);
     });
     for (td_ctx* c : mem) pr.push_back(problem(c->Sinv, np, c->Dm, np, c->A, np, np, np, np, T, 0));
@@ -1765,6 +1788,12 @@ td_status td_get_energy(td_ctx* ctx, const double field[3], double* energy) {
                                field ? c->scal + SC_FIELD : nullptr, c->na, c->scal + SC_E));
     double e[3];
     read_scal(c, SC_E, e, 3);
+    double e_rep = 0.0;
+    if (c->ehr && c->rep_a) {   // moving nuclei: the pair repulsion at the current positions
+      HIPCHK(c, td::repulsion(c->stream, c->pos, c->species, c->rep_a, c->nsp, c->rep_decay,
+                              c->na, nullptr, c->e_rep_atom, c->scal + SC_EREP));
+      read_scal(c, SC_EREP, &e_rep, 1);
+    }
     double e_u = 0.0;
     if (c->plus_u != TD_PLUS_U_NONE) {
       // correction energy (Sec. 3.2, Eq. 21 or 24) of the current density
@@ -1780,7 +1809,7 @@ td_status td_get_energy(td_ctx* ctx, const double field[3], double* energy) {
       sync(c);
       for (double x : es) e_u += x;
     }
-    *energy = e[0] + e[1] + e[2] + e_u;
+    *energy = e[0] + e[1] + e[2] + e_rep + e_u;
   });
 }
 
@@ -1930,15 +1959,16 @@ td_status td_get_energy_series(td_ctx* ctx, double* e_el, double* e_kin, int32_t
     REQUIRE(c, c->ehr, TD_ENOTSUP, "clamped-nuclei context");
     REQUIRE(c, n_out && cap >= 0 && ((e_el && e_kin) || cap == 0), TD_EINVAL, "invalid output");
     const int k = std::min(cap, c->last_n);
-    std::vector<double> parts(3 * (size_t)std::max(k, 1));
+    std::vector<double> parts(4 * (size_t)std::max(k, 1));
     if (k > 0) {
-      HIPCHK(c, hipMemcpyAsync(parts.data(), c->e_el, sizeof(double) * 3 * k,
+      HIPCHK(c, hipMemcpyAsync(parts.data(), c->e_el, sizeof(double) * 4 * k,
                                hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipMemcpyAsync(e_kin, c->e_kin, sizeof(double) * k, hipMemcpyDeviceToHost,
                                c->stream));
     }
     sync(c);
-    for (int i = 0; i < k; ++i) e_el[i] = parts[3 * i] + parts[3 * i + 1] + parts[3 * i + 2];
+    for (int i = 0; i < k; ++i)
+      e_el[i] = parts[4 * i] + parts[4 * i + 1] + parts[4 * i + 2] + parts[4 * i + 3];
     *n_out = c->last_n;
   });
 }

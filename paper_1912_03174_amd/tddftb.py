@@ -193,7 +193,7 @@ class TdModel(ctypes.Structure):
     _fields_ = [("n_species", ctypes.c_int32), ("species", _ip), ("species_norb", _ip),
                 ("sk_s", _dp), ("sk_h", _dp), ("decay", ctypes.c_double), ("scale_s", _dp),
                 ("scale_h", _dp), ("onsite", _dp), ("hubbard_u", ctypes.c_double),
-                ("mass", _dp)]
+                ("mass", _dp), ("rep_a", _dp), ("rep_decay", ctypes.c_double)]
 
 
 class TdBatchInfo(ctypes.Structure):
@@ -307,11 +307,15 @@ def _model_struct(model: dict, keep):
     keep.scale_h = _f64(model["scale_h"])
     keep.onsite = _f64(model["onsite"])
     keep.mass = _f64(model["mass"])
+    rep = model.get("rep_a")
+    keep.rep_a = None if rep is None else _f64(rep)
     return TdModel(n_species=len(keep.norb), species=_ptr(keep.species, np.int32),
                    species_norb=_ptr(keep.norb, np.int32), sk_s=_ptr(keep.sk_s),
                    sk_h=_ptr(keep.sk_h), decay=float(model["decay"]), scale_s=_ptr(keep.scale_s),
                    scale_h=_ptr(keep.scale_h), onsite=_ptr(keep.onsite),
-                   hubbard_u=float(model["hubbard_u"]), mass=_ptr(keep.mass))
+                   hubbard_u=float(model["hubbard_u"]), mass=_ptr(keep.mass),
+                   rep_a=None if rep is None else _ptr(keep.rep_a),
+                   rep_decay=float(model.get("rep_decay", 0.0)))
 
 
 def td_create_ehrenfest(system, model: dict, velocities=None, options: Optional[TdOptions] = None,

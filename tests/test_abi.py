@@ -161,6 +161,16 @@ def test_ehrenfest_arguments_rejected_before_device(T):
     with pytest.raises(T.TdError) as e:
         T.td_create_ehrenfest(s, dict(m, species=np.zeros(s.n_atoms, dtype=np.int32)))
     assert e.value.status == T.TD_EINVAL
+    # the pair repulsion: negative, asymmetric, non-finite amplitudes; no decay
+    bad = [np.array([[1.0, -0.1], [-0.1, 1.0]]), np.array([[1.0, 0.2], [0.3, 1.0]]),
+           np.array([[1.0, np.inf], [np.inf, 1.0]])]
+    for rep in bad:
+        with pytest.raises(T.TdError) as e:
+            T.td_create_ehrenfest(s, dict(m, rep_a=rep))
+        assert e.value.status == T.TD_EINVAL and "rep" in str(e.value)
+    with pytest.raises(T.TdError) as e:
+        T.td_create_ehrenfest(s, dict(m, rep_decay=0.0))
+    assert e.value.status == T.TD_EINVAL and "rep" in str(e.value)
 
 
 class _PU:

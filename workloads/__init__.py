@@ -286,6 +286,14 @@ def pair_scales(n_atoms, seed):
     return jit_s, jit_h
 
 
+# Pair repulsion of the two-centre model, V_AB(r) = a exp(-r / REP_DECAY)
+# (hartree, bohr): the model's repulsive energy (Sec. 2.1), a short-range
+# wall whose amplitudes were fitted by tests/golden/fit_repulsion.py (oracle
+# forces of the 499-atom strip's ground state; stored here as constants).
+REP_DECAY = 0.5
+REP_A = {"CC": 18.837233, "CH": 5.910942, "HH": 5.910942}
+
+
 def two_centre_model(system: System) -> dict:
     """The parameters S and H0 of ``system`` are built from, as plain arrays,
     so S(R) and H0(R) can be rebuilt at other positions (moving nuclei).
@@ -296,7 +304,8 @@ def two_centre_model(system: System) -> dict:
     integral is prefactor x exp(-r / decay) x the Slater-Koster angular
     factor (direction cosines from the first atom to the second) x the
     pair's scale factor. ``onsite`` [2, 2]: H0 on-site s and p energies.
-    ``mass`` in electron masses."""
+    ``mass`` in electron masses. ``rep_a`` [2, 2] and ``rep_decay``: the
+    pair repulsion a[s_A, s_B] exp(-r / rep_decay)."""
     idx = {"C": 0, "H": 1}
     sk_s = np.zeros((2, 2, 4))
     sk_h = np.zeros((2, 2, 4))
@@ -314,6 +323,8 @@ def two_centre_model(system: System) -> dict:
         onsite=np.array([[ONSITE["s"], ONSITE["p"]], [ONSITE["s"], ONSITE["p"]]]),
         hubbard_u=HUBBARD_U,
         mass=np.array([MASS_AMU["C"], MASS_AMU["H"]]) * AMU,
+        rep_a=np.array([[REP_A["CC"], REP_A["CH"]], [REP_A["CH"], REP_A["HH"]]]),
+        rep_decay=REP_DECAY,
     )
 
 
@@ -484,13 +495,19 @@ def workload(cfg: int) -> Workload:
 def ehrenfest_workload() -> Workload:
     """Moving-nuclei pump run: 499-atom 7-line armchair strip (C383H116,
     N_orb = 1648), nuclei at 300 K (thermal_velocities seed 5000), sin^2 pump
-    0.15 Ha, 0.01 au, t_p = 10 fs along the strip, 5000 steps of 0.2 au."""
+    0.15 Ha, 0.01 au, t_p = 10 fs, in-plane across the strip (y), 5000 steps
+    of 0.2 au. Across, not along: the strip is 223 bohr long, and a 0.01 au
+    field along it would spread the atomic potentials R . E over 2.2 Ha,
+    which with the 3.7 Ha wide spectrum of S^-1 H takes dt times the width
+    past the leapfrog's limit of 1 at the pump's peak (18 bohr across:
+    0.18 Ha)."""
     s = small_strip(54, 0, seed=1005, width=3)
     t_p = 10.0 * FS
     return Workload("strip1648md", s, dt=0.2, n_steps=5000, kick=None,
-                    laser=dict(e0=0.01, omega=0.15, t_p=t_p, direction=(1.0, 0.0, 0.0)),
+                    laser=dict(e0=0.01, omega=0.15, t_p=t_p, direction=(0.0, 1.0, 0.0)),
                     description="C383H116 strip, N_orb=1648, moving nuclei at 300 K, sin^2 "
-                                "pump 0.15 Ha, 0.01 au, 10 fs, 5000 steps of 0.2 au")
+                                "pump 0.15 Ha, 0.01 au, 10 fs across the strip, 5000 steps "
+                                "of 0.2 au")
 
 
 def spectrum_workload() -> Workload:
