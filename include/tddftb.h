@@ -209,8 +209,10 @@ TD_API td_status td_kick(td_ctx *ctx, double e0, const double dir[3]);
  * density matrix of this call. The dipole of each density entering a
  * step is recorded (see td_get_dipole_series). Returns TD_EUNSTABLE
  * before any step when dt times the width of the spectrum of S^-1 H (a
- * lower bound taken at creation, td_info.width_estimate) is 1 or more,
- * where the leapfrog diverges (Sec. 2.3, Eq. 19); and after the steps if
+ * lower bound taken at creation, td_info.width_estimate), plus with a
+ * field the largest spread of the field's potential R_A . E over the atoms
+ * (current positions) among this call's steps, is 1 or more, where the
+ * leapfrog diverges (Sec. 2.3, Eq. 19); and after the steps if
  * the state became non-finite or its electron count Tr(rho S), which the
  * leapfrog keeps, moved by more than 1e-6 N_e since creation, the last
  * kick or restore (1e-3 N_e with moving nuclei; in split-bf16 precision,

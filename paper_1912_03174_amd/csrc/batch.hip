@@ -419,6 +419,19 @@ void step_impl(td_batch* b, int n, const double* field) {
   if (field) {
     for (size_t i = 0; i < 3 * (size_t)n; ++i)
       REQUIRE(b, std::isfinite(field[i]), TD_EINVAL, "non-finite field");
+    // with the spread of the field's potential over each member's atoms
+    for (int m = 0; m < b->nm; ++m) {
+      const td_ctx* c = b->mem[m];
+      const double spread = tdi::field_spread(c, field, n);
+      const double st = c->opt.dt * (c->info.width_estimate + spread);
+      if (!(st < 1.0)) {
+        b->err = "member " + std::to_string(m) + ": time step " + std::to_string(c->opt.dt) +
+                 " too large for the leapfrog under this field: dt times the width of the "
+                 "spectrum of S^-1 H plus the spread of R . E over the atoms is " +
+                 std::to_string(st) + " (must be below 1)";
+        throw Fail{TD_EUNSTABLE};
+      }
+    }
   }
   if (b->ehr) {
     ehr_step_impl(b, n, field);

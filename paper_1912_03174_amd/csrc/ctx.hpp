@@ -165,6 +165,9 @@ void ehr_batch_steps(std::vector<td_ctx*>& mem, EhrGroup& g, int nsteps, const d
                      std::string& err);
 // Device series for nsteps dipoles and energies.
 void ensure_series_ctx(td_ctx* c, int nsteps);
+// Largest spread over the atoms (current host positions) of the field's
+// potential R_A . E_k over the steps of `field` [nsteps x 3].
+double field_spread(const td_ctx* c, const double* field, int nsteps);
 
 // Waits for the context's stream.
 void sync_ctx(td_ctx* c);

@@ -1134,7 +1134,22 @@ void step_impl(td_ctx* c, int nsteps, const double* field) {
     c->last_n = 0;     // an empty call records no dipoles (or energies)
     return;
   }
-  if (field) REQUIRE(c, finite_all(field, 3 * (size_t)nsteps), TD_EINVAL, "non-finite field");
+  if (field) {
+    REQUIRE(c, finite_all(field, 3 * (size_t)nsteps), TD_EINVAL, "non-finite field");
+    // the field's potential R_A . E widens the spectrum of S^-1 H by about
+    // its spread over the atoms (Sec. 2.1, Eq. 7)
+    const double spread = tdi::field_spread(c, field, nsteps);
+    const double st = c->opt.dt * (c->info.width_estimate + spread);
+    if (!(st < 1.0)) {
+      char msg[300];
+      std::snprintf(msg, sizeof(msg),
+                    "time step %.4g too large for the leapfrog under this field: the spectrum of "
+                    "S^-1 H is at least %.4g wide, the field spreads the atomic potentials R . E "
+                    "over up to %.4g, and dt times their sum is %.3g (must be below 1)",
+                    c->opt.dt, c->info.width_estimate, spread, st);
+      REQUIRE(c, false, TD_EUNSTABLE, msg);
+    }
+  }
   const int na = c->na, np = c->np;
   if (field && c->field_cap < nsteps) {
     if (c->field) (void)hipFree(c->field);
@@ -1696,6 +1711,22 @@ void ehr_batch_steps(std::vector<td_ctx*>& mem, EhrGroup& g, int nsteps, const d
 }
 
 void ensure_series_ctx(td_ctx* c, int nsteps) { ensure_series(c, nsteps); }
+
+double field_spread(const td_ctx* c, const double* field, int nsteps) {
+  double spread = 0.0;
+  const double* p = c->pos_h.data();
+  for (int k = 0; k < nsteps; ++k) {
+    const double* E = field + 3 * (size_t)k;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int a = 0; a < c->na; ++a) {
+      const double v = p[3 * a] * E[0] + p[3 * a + 1] * E[1] + p[3 * a + 2] * E[2];
+      lo = std::min(lo, v);
+      hi = std::max(hi, v);
+    }
+    spread = std::max(spread, hi - lo);
+  }
+  return spread;
+}
 }  // namespace tdi
 
 extern "C" {

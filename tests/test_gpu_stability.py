@@ -84,6 +84,36 @@ def test_leapfrog_limit_refused_before_any_step(flake):
     under.close()
 
 
+def test_field_spread_counts_against_the_leapfrog_limit(flake):
+    """A field's potential R_A . E spreads the diagonal of H over the atoms
+    and so widens the spectrum the leapfrog must resolve: a field whose
+    spread takes dt (width + spread) past 1 is refused before any step, by
+    one trajectory and by a batch, with the state untouched; at 90% of that
+    spread the run proceeds."""
+    T = _T()
+    s, gs, width = flake
+    dt = 0.2
+    x = s.positions[:, 0]
+    limit = (1.0 / dt - width) / (x.max() - x.min())      # field along x at the limit
+    say(f"field spread limit flake: width {width:.3f}, limit field {limit:.3f} au")
+    too = np.tile([1.05 * limit, 0.0, 0.0], (3, 1))
+    fine = np.tile([0.9 * limit, 0.0, 0.0], (3, 1))
+    p = T.Propagator(s, rho0=gs.rho, dt=dt)
+    with pytest.raises(T.TdError) as e:
+        p.step(3, too)
+    assert e.value.status == T.TD_EUNSTABLE and "under this field" in str(e.value)
+    assert p.info()["step"] == 0
+    p.step(3, fine)
+    assert p.info()["step"] == 3
+    p.close()
+    b = T.Batch([s], rho0s=[gs.rho], dt=dt)
+    with pytest.raises(T.TdError) as e:
+        b.step(3, too)
+    assert e.value.status == T.TD_EUNSTABLE and "under this field" in str(e.value)
+    b.step(3, fine)
+    b.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "split"])
 def test_electron_count_drift_is_reported(flake, precision):
     """A restored history whose previous density holds 0.1% more electrons
