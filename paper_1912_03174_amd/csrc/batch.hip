@@ -48,6 +48,7 @@ struct td_batch {
   int64_t step = 0;
   int last_n = 0;
   // device tables
+  std::vector<td::BatchMember> mem_h;   // host copy of the member table
   td::BatchMember* mem_d = nullptr;
   td::BatchItem* rows_d = nullptr;
   td::BatchItem* atoms_d = nullptr;
@@ -142,8 +143,16 @@ int number_tiles(std::vector<td::GemmProblem>& v) {
   return t;
 }
 
-// Device tables of the products for the current bucket -> tile choice.
+// Device tables of the products for the current bucket -> tile choice,
+// and the columns of H each member's S^-1 H product reads.
 void build_products(td_batch* b) {
+  for (int m = 0; m < b->nm; ++m) {
+    const td_ctx* c = b->mem[m];
+    const int T = b->bucket_tile[b->bucket[m]];
+    b->mem_h[m].hw = T == 128 ? c->np : std::min(c->np, round_up(c->n, T));
+  }
+  HIPCHK(b, hipMemcpyAsync(b->mem_d, b->mem_h.data(), sizeof(td::BatchMember) * b->mem_h.size(),
+                           hipMemcpyHostToDevice, b->stream));
   for (int v = 0; v < 2; ++v) {
     std::vector<td::GemmProblem> g1, g2[2];
     for (int m = 0; m < b->nm; ++m) {
@@ -346,7 +355,11 @@ void create_impl(td_batch* b, int n, const td_system* systems, const td_options*
     M.vorb = c->vorb;
     M.np = c->np;
     M.na = c->na;
-    for (int r = 0; r < c->np; ++r) rows.push_back({m, r});
+    M.kw = round_up(c->n, 16);
+    M.hw = c->np;            // narrowed to the product's tile span once tiles are chosen
+    // rows of the charges and of H: the products read H rows below K =
+    // round_up(n, 16) only, and the charges use the rows of real orbitals
+    for (int r = 0; r < M.kw; ++r) rows.push_back({m, r});
     for (int a = 0; a < c->na; ++a) atoms.push_back({m, a});
     const int nt = round_up(c->n, 32) / 32;   // tiles beyond n stay zero
     for (int i = 0; i < nt; ++i)
@@ -357,6 +370,7 @@ void create_impl(td_batch* b, int n, const td_system* systems, const td_options*
   b->nrows = (int)rows.size();
   b->natoms = (int)atoms.size();
   b->npairs = (int)pairs.size();
+  b->mem_h = bm;
   upload(b, &b->mem_d, bm);
   upload(b, &b->rows_d, rows);
   upload(b, &b->atoms_d, atoms);

@@ -27,7 +27,10 @@ __global__ __launch_bounds__(256) void k_b_rowdot(const BatchMember* __restrict_
   const double2* x = reinterpret_cast<const double2*>(M.R[cur] + (size_t)it.r * 2 * np);
   const double2* y = reinterpret_cast<const double2*>(M.S + (size_t)it.r * np);
   double acc = 0.0;
-  for (int c = l; c < np / 2; c += WAVE) {
+  // the one-trajectory row dot runs over all np columns; the terms from
+  // kw on are products with zero density entries and leave every partial
+  // sum unchanged
+  for (int c = l; c < M.kw / 2; c += WAVE) {
     const double2 a = x[c], b = y[c];
     acc = fma(a.x, b.x, acc);
     acc = fma(a.y, b.y, acc);
@@ -99,7 +102,7 @@ __global__ __launch_bounds__(256) void k_b_assemble(const BatchMember* __restric
   const size_t base2 = (size_t)it.r * np / 2;
   const double* vorb = M.vorb;
   const double vr = vorb[it.r];
-  for (int c2 = l; c2 < np / 2; c2 += WAVE) {
+  for (int c2 = l; c2 < M.hw / 2; c2 += WAVE) {
     const double2 h0 = reinterpret_cast<const double2*>(M.H0)[base2 + c2];
     const double2 s = reinterpret_cast<const double2*>(M.S)[base2 + c2];
     const int c = 2 * c2;

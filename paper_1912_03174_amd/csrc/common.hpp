@@ -76,6 +76,8 @@ struct BatchMember {
   double* v;
   double* vorb;
   int np, na;
+  int kw;   // columns of the Mulliken row dots: round_up(n, 16); beyond, rho is zero
+  int hw;   // columns of H assembled: those the S^-1 H product reads (its tile span)
 };
 struct BatchItem {        // row (or atom) r of member m
   int m, r;
