@@ -101,6 +101,37 @@ def test_split_flake_laser_and_energy(flake):
     p.close()
 
 
+@pytest.mark.parametrize("which,slices", [("dimer", 4), ("benzene", 4), ("strip314", 4),
+                                          ("strip648", 4), ("strip314", 5)])
+def test_split_ragged_sizes(which, slices):
+    """Split runs from one orbital pair to several 128-tiles plus a ragged
+    tail, against the oracle: padded sizes 128 and 384 (K segments that are
+    not whole multiples of 256) and 768 (whole multiples), and five slices
+    through the eight-wave product's two-stage form."""
+    T = _T()
+    s = {"dimer": lambda: W.dimer(u=1.0),
+         "benzene": lambda: W.benzene(),
+         "strip314": lambda: W.small_strip(8, 4, seed=1),
+         "strip648": lambda: W.small_strip(20, 10, seed=1)}[which]()
+    say(f"split ragged {which} n_orb={s.n_orb} slices={slices}")
+    gs = O.ground_state(s, tol=1e-13)
+    Sinv = O.inverse_overlap(s.S)
+    rk = O.kick(gs.rho, s.S, Sinv, s.positions, s.orb_offset, 1e-3, (1.0, 1.0, 0.0))
+    ref = O.propagate(s, rk, 200, 0.2, Sinv=Sinv, record_energy=False)
+    p = T.Propagator(s, rho0=gs.rho, precision=T.TD_SPLIT_BF16, n_slices=slices)
+    p.kick(1e-3, (1.0, 1.0, 0.0))
+    mu = p.step(200)
+    err = dipole_rel_err(mu, ref.dipoles)
+    say(f"split ragged {which} dipole relative error {err:.3e}")
+    assert err < 1e-6
+    dq_ref = O.charge_fluctuations(ref.rho, s.S, s.orb_offset, s.q0)
+    assert np.abs(p.charges() - dq_ref).max() < 1e-6 * np.abs(dq_ref - gs.dq).max() + 1e-12
+    rho = p.rho()[0]
+    assert np.abs(rho - rho.conj().T).max() == 0.0
+    assert abs(np.real(np.trace(rho @ s.S)) - s.n_elec) < 1e-10
+    p.close()
+
+
 def test_split_checkpoint_round_trip(flake):
     T = _T()
     s, gs, _ = flake
